@@ -1,0 +1,216 @@
+/*
+ * heom.h — C ABI of the MI355X (gfx950) HEOM library.
+ *
+ * The library evaluates the hierarchical equations of motion (eq. HEOM of the
+ * section "HEOM formalism" of Kramer et al., "Efficient calculation of open
+ * quantum system dynamics and time-resolved spectroscopy with Distributed
+ * Memory HEOM (DM-HEOM)", arXiv:1803.03498) for a Frenkel-exciton Hamiltonian
+ * (eq. h-ex) coupled to Drude-Lorentz baths (eq. spectral_density_DL with
+ * Omega = 0) expanded in Matsubara terms, and integrates them with classic
+ * RK4 (four right-hand-side evaluations per step, section "Distributed memory
+ * HEOM implementation").
+ *
+ * Conventions used throughout:
+ *   - Units at the boundary: energies in cm^-1, times in fs, temperature in K.
+ *     Internally hbar = 1 and energies are angular frequencies in rad/fs.
+ *   - A hierarchy member ("ADO") sigma_u is an N x N complex matrix, row-major,
+ *     real and imaginary parts interleaved.  u = 0 is the reduced density
+ *     matrix rho = sigma_0.  ADOs are numbered by level |n| = 0..D and, inside a
+ *     level, by descending lexicographic order of the index tuple n.
+ *   - Mode l of the tuple is bath b, Matsubara term k: l = (sum of (1 + M_b')
+ *     over baths b' < b) + k, 0-based (the paper's l = (b-1)K + k + 1 when
+ *     every bath has K = 1 + M modes).
+ *   - Device memory is always owned by the caller: every call that needs
+ *     device memory takes a pointer and a size obtained from heom_plan (or the
+ *     size helpers below).  The library never allocates device memory.
+ *   - Streams are hipStream_t values passed as void* (NULL = default stream).
+ *     Work is enqueued on that stream; calls documented as synchronous wait
+ *     for the stream before returning.
+ *   - Every call returns a heom_status.  On failure heom_last_error() returns a
+ *     thread-local message.  No C++ exception crosses the ABI.
+ */
+#ifndef HEOM_H
+#define HEOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t heom_status;
+
+enum {
+    HEOM_OK = 0,
+    HEOM_PENDING = 1,         /* heom_poll: the request has not finished      */
+    HEOM_E_INVAL = -1,        /* invalid argument or problem                  */
+    HEOM_E_RANGE = -2,        /* sizes overflow (n_ado >= 2^31, N > 64, ...)  */
+    HEOM_E_NOMEM = -3,        /* caller buffer too small / can never fit      */
+    HEOM_E_DEVICE = -4,       /* HIP runtime error or no gfx950 device        */
+    HEOM_E_NUMERIC = -5,      /* NaN/Inf seen by an FP64 observable reduction */
+    HEOM_E_UNSTABLE = -6,     /* dt times the rate bound leaves RK4's region  */
+    HEOM_E_NOTFOUND = -7,     /* unknown ticket                               */
+    HEOM_E_CANCELLED = -8     /* request cancelled before it finished         */
+};
+
+/* Precision of the hierarchy state. */
+enum {
+    HEOM_FP64 = 0,        /* every ADO complex128                                   */
+    HEOM_FP32_MIXED = 1   /* sigma_0 complex128 with FP64 RK4 and FP64 observables; */
+                          /* ADOs u >= 1 complex64 with FP32 arithmetic             */
+};
+
+/* Test switches (heom_problem.flags).  Both the library and the oracle honour them. */
+enum {
+    HEOM_FLAG_NO_RESCALE = 1u,     /* plain couplings i V^x and n theta instead of the
+                                      rescaled ones (substitution of section "HEOM
+                                      formalism") */
+    HEOM_FLAG_NO_TERMINATOR = 2u,  /* drop the third line of eq. HEOM                  */
+    HEOM_FLAG_ADD_REORG = 4u,      /* add lambda_b to H[s_b][s_b] (eq. h-ex)           */
+    HEOM_FLAG_STANDARD_GAUGE = 8u  /* flip the sign of both coupling lines             */
+};
+
+/* Observables recorded from sigma_0 (FP64). */
+enum {
+    HEOM_OBS_POPULATION = 0, /* record = [Re rho_mm (m < N), Re Tr, Im Tr, max|rho - rho^+|] */
+    HEOM_OBS_DIPOLE = 1      /* record = [Re P, Im P, Re Tr, Im Tr], P = sum_a mu_a rho[a][g]
+                                (polarisation of eq. polarization with mu^+ of eq.
+                                mu_plusp, section "Optical spectra") */
+};
+
+/* One Drude-Lorentz bath (eq. spectral_density_DL, Omega = 0) coupled to the
+ * projector |state><state| (section "Frenkel exciton model"). */
+typedef struct {
+    int32_t state;        /* 0 <= state < n_states                        */
+    int32_t n_matsubara;  /* M >= 0: the bath contributes 1 + M modes     */
+    double lambda_cm;     /* reorganisation energy lambda >= 0, cm^-1     */
+    double tau_fs;        /* nu^-1 > 0, fs                                */
+} heom_bath;
+
+typedef struct {
+    int32_t n_states;       /* N, 1..64                                         */
+    int32_t n_baths;        /* B >= 0                                           */
+    const double* h_re_cm;  /* [N*N] row-major Hermitian H, cm^-1 (required)    */
+    const double* h_im_cm;  /* [N*N] or NULL for a real symmetric H             */
+    const heom_bath* baths; /* [B]                                              */
+    double temperature_K;   /* T > 0                                            */
+    int32_t depth;          /* truncation depth D >= 0 (sum of tuple <= D)      */
+    int32_t precision;      /* HEOM_FP64 or HEOM_FP32_MIXED                     */
+    uint32_t flags;         /* HEOM_FLAG_*                                      */
+} heom_problem;
+
+/* Sizes of a problem (heom_plan). */
+typedef struct {
+    int64_t n_ado;          /* C(W + D, W), eq. Nmatrices                 */
+    int64_t n_plus_edges;   /* number of valid "+" links                  */
+    int32_t n_states;       /* N                                          */
+    int32_t n_modes;        /* W = sum over baths of (1 + M_b)            */
+    int32_t depth;          /* D                                          */
+    int32_t elem_bytes;     /* bytes per complex element of ADOs u >= 1   */
+    size_t tables_bytes;    /* device bytes for heom_build_hierarchy      */
+    size_t sigma0_bytes;    /* N*N*16                                     */
+    size_t rest_bytes;      /* (n_ado - 1) * N*N * elem_bytes             */
+    size_t work_bytes;      /* device workspace of heom_propagate without
+                               records (three RK4 stage copies + control) */
+} heom_info;
+
+/* A hierarchy state: sigma_0 (complex128 [N][N]) and ADOs 1..n_ado-1
+ * (complex128 or complex64 [n_ado-1][N][N] by precision).  Both device
+ * pointers, 256-byte aligned, caller-owned.  In HEOM_FP64, rest may equal
+ * sigma0 + N*N complex elements (one contiguous array). */
+typedef struct {
+    void* sigma0;
+    void* rest;
+} heom_state;
+
+typedef struct {
+    int32_t kind;        /* HEOM_OBS_*                                         */
+    int32_t ground;      /* HEOM_OBS_DIPOLE: index g of the ground state       */
+    const double* mu;    /* HEOM_OBS_DIPOLE: host [N] projected dipoles e_p.d_a */
+} heom_observable;
+
+typedef struct heom_hierarchy heom_hierarchy;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* heom_last_error(void);
+/* Static name of a status code. */
+const char* heom_status_string(heom_status s);
+
+/* Host only (no device call): validate a problem and report its sizes.
+ * Validation (HEOM_E_INVAL): N in 1..64, D >= 0, B >= 0, bath states in
+ * [0, N), lambda >= 0, tau > 0, M >= 0, T > 0, finite inputs, H Hermitian to
+ * 1e-12 relative, no Matsubara rate equal to nu.  HEOM_E_RANGE if
+ * n_ado >= 2^31 or W > 255 or D > 255. */
+heom_status heom_plan(const heom_problem* problem, heom_info* info);
+
+/* Bytes per record and records produced by a propagation (step 0 plus every
+ * record_every-th step). */
+int32_t heom_record_doubles(int32_t n_states, int32_t kind);
+int64_t heom_record_count(int64_t n_steps, int32_t record_every);
+/* Device workspace for heom_propagate: info->work_bytes plus the records. */
+size_t heom_propagate_work_bytes(const heom_info* info, int64_t n_steps, int32_t record_every,
+                                 int32_t kind);
+
+/* Build the hierarchy on the device: bath coefficients (host FP64, section
+ * "HEOM formalism": gamma(b,k), c(b,k), the correction coefficient of the third
+ * line, rescaled coupling weights), then on the GPU the tuple enumeration of
+ * eq. Nmatrices, the +/- link tables ("computed in a first step") and the
+ * per-ADO damping sum_l n_l gamma_l.  tables_dev must hold info.tables_bytes
+ * bytes and stay valid until heom_destroy.  Asynchronous on `stream`; the
+ * problem struct may be freed on return.  *out receives a handle. */
+heom_status heom_build_hierarchy(const heom_problem* problem, void* tables_dev,
+                                 size_t tables_bytes, void* stream, heom_hierarchy** out);
+
+/* Synchronous: copy the tables to host buffers (any may be NULL):
+ * tuples uint8 [n_ado][W], plus/minus int32 [n_ado][W] (-1 = absent link),
+ * level uint8 [n_ado]. */
+heom_status heom_copy_tables(const heom_hierarchy* h, uint8_t* tuples, int32_t* plus,
+                             int32_t* minus, uint8_t* level, void* stream);
+
+/* Host copy of the per-mode coefficients (FP64, hbar = 1): gamma [W] (1/fs),
+ * c [W] (rad/fs^2), lambda*nu [W] (0 for k > 0), and delta [N] (the correction
+ * coefficient summed per state, 1/fs).  Any pointer may be NULL. */
+heom_status heom_coefficients(const heom_hierarchy* h, double* gamma, double* c, double* lamnu,
+                              double* delta_state);
+
+/* One evaluation out = f(in) of eq. HEOM (with the rescaled couplings unless
+ * HEOM_FLAG_NO_RESCALE) over every ADO.  in and out must not overlap.
+ * Asynchronous.  hermitian != 0 asserts that every ADO of `in` is Hermitian:
+ * the kernels then read the column s of a neighbour as the conjugate of its
+ * row s (otherwise the result is undefined). */
+heom_status heom_rhs(const heom_hierarchy* h, heom_state in, heom_state out, int32_t hermitian,
+                     void* stream);
+
+/* Advance `io` by n_steps classic RK4 steps of dt_fs:
+ *   Y2 = y + dt/2 f(y), Y3 = y + dt/2 f(Y2), Y4 = y + dt f(Y3),
+ *   y' = (-y + Y2 + 2 Y3 + Y4)/3 + dt/6 f(Y4),
+ * the textbook step rewritten so that each stage reads one ADO array with its
+ * neighbours and writes the next.  work_dev (heom_propagate_work_bytes) holds
+ * the three stage copies, the records and a status word.  Observables of
+ * sigma_0 are reduced in FP64 at step 0 and every record_every steps.
+ * hermitian: as for heom_rhs, for the initial state (it is preserved).
+ * Synchronous: returns after the stream has finished; if host_out != NULL
+ * the records are copied to host_out [n_rec][heom_record_doubles].
+ * HEOM_E_UNSTABLE if dt exceeds the RK4 bound for the problem's rates;
+ * HEOM_E_NUMERIC if a recorded observable was not finite. */
+heom_status heom_propagate(const heom_hierarchy* h, heom_state io, void* work_dev,
+                           size_t work_bytes, double dt_fs, int64_t n_steps, int32_t record_every,
+                           const heom_observable* obs, int32_t hermitian, double* host_out,
+                           void* stream);
+
+/* Checkpoint / resume of a state: synchronous device <-> host copies of
+ * sigma_0 (complex128 [N][N]) and the ADOs u >= 1 (element type by precision). */
+heom_status heom_get_state(const heom_hierarchy* h, heom_state s, void* host_sigma0,
+                           void* host_rest, void* stream);
+heom_status heom_set_state(const heom_hierarchy* h, heom_state s, const void* host_sigma0,
+                           const void* host_rest, void* stream);
+
+/* Release a handle (does not touch caller memory). */
+heom_status heom_destroy(heom_hierarchy* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HEOM_H */

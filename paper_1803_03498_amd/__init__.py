@@ -1,0 +1,205 @@
+"""MI355X (gfx950) HEOM library: Python binding of the C ABI in include/heom.h.
+
+The right-hand side of the hierarchical equations of motion (Kramer et al.,
+arXiv:1803.03498, section "HEOM formalism", eq. HEOM) and its classic RK4
+integration run in hand-written HIP kernels inside ``libheom.so``.  This module
+only marshals arguments: PyTorch provides device memory and the stream, and
+every step of the computation happens in the library.  There is no CPU
+fallback: without the built library (or without a gfx950 GPU) the calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _abi
+from ._abi import FP32_MIXED, FP64, OBS_DIPOLE, OBS_POPULATION, HeomError, check, load
+
+__all__ = ["FP64", "FP32_MIXED", "OBS_POPULATION", "OBS_DIPOLE", "HeomError", "Problem", "plan",
+           "Hierarchy", "load"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Problem:
+    """A problem dict (see heom_inputs) packed into a heom_problem struct."""
+
+    def __init__(self, prob, precision=FP64):
+        H = np.asarray(prob["H"])
+        self.N = int(H.shape[0])
+        self._h_re = np.ascontiguousarray(H.real, dtype=np.float64)
+        self._h_im = (np.ascontiguousarray(H.imag, dtype=np.float64)
+                      if np.iscomplexobj(H) else None)
+        baths = prob["baths"]
+        self._baths = (_abi.HeomBath * max(1, len(baths)))()
+        for k, b in enumerate(baths):
+            self._baths[k] = _abi.HeomBath(int(b["state"]), int(b["matsubara"]),
+                                           float(b["lambda_cm"]), float(b["tau_fs"]))
+        dp = ctypes.POINTER(ctypes.c_double)
+        self.struct = _abi.HeomProblem(
+            self.N, len(baths), self._h_re.ctypes.data_as(dp),
+            self._h_im.ctypes.data_as(dp) if self._h_im is not None else None,
+            self._baths, float(prob["temperature_K"]), int(prob["depth"]), int(precision),
+            int(prob.get("flags", 0)))
+        self.precision = int(precision)
+
+
+def plan(prob, precision=FP64):
+    """heom_plan: sizes of a problem as a dict (host only, no GPU needed)."""
+    p = prob if isinstance(prob, Problem) else Problem(prob, precision)
+    info = _abi.HeomInfo()
+    check(load().heom_plan(ctypes.byref(p.struct), ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in _abi.HeomInfo._fields_}
+
+
+def _info_struct(d):
+    info = _abi.HeomInfo()
+    for f, _ in _abi.HeomInfo._fields_:
+        setattr(info, f, d[f])
+    return info
+
+
+class Hierarchy:
+    """A hierarchy built on the current GPU (heom_build_hierarchy)."""
+
+    def __init__(self, prob, precision=FP64, stream=None):
+        torch = _torch()
+        self.problem = Problem(prob, precision)
+        self.precision = int(precision)
+        self.info = plan(self.problem)
+        self.N = self.problem.N
+        self.n_ado = int(self.info["n_ado"])
+        self.W = int(self.info["n_modes"])
+        self.tables_dev = torch.empty(self.info["tables_bytes"], dtype=torch.uint8, device="cuda")
+        h = ctypes.c_void_p()
+        check(load().heom_build_hierarchy(ctypes.byref(self.problem.struct),
+                                          ctypes.c_void_p(self.tables_dev.data_ptr()),
+                                          self.info["tables_bytes"], _stream_handle(stream),
+                                          ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                load().heom_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    # -------------------------------------------------------------- state --
+    @property
+    def rest_dtype(self):
+        torch = _torch()
+        return torch.complex128 if self.precision == FP64 else torch.complex64
+
+    def new_state(self, rho0=None):
+        """(sigma0 complex128 [N,N], rest [n_ado-1,N,N]) on the GPU, zeroed;
+        sigma0 set to rho0 if given."""
+        torch = _torch()
+        s0 = torch.zeros((self.N, self.N), dtype=torch.complex128, device="cuda")
+        rest = torch.zeros((max(self.n_ado - 1, 0), self.N, self.N), dtype=self.rest_dtype,
+                           device="cuda")
+        if rho0 is not None:
+            s0.copy_(torch.as_tensor(np.asarray(rho0, dtype=np.complex128)))
+        return s0, rest
+
+    def state_from_numpy(self, full):
+        """Device state from a numpy complex array [n_ado, N, N]."""
+        torch = _torch()
+        full = np.asarray(full)
+        s0 = torch.as_tensor(np.ascontiguousarray(full[0], dtype=np.complex128)).cuda()
+        rest = torch.as_tensor(np.ascontiguousarray(
+            full[1:], dtype=np.complex128 if self.precision == FP64 else np.complex64)).cuda()
+        return s0, rest
+
+    @staticmethod
+    def state_to_numpy(state):
+        s0, rest = state
+        out = np.zeros((1 + rest.shape[0],) + tuple(s0.shape), np.complex128)
+        out[0] = s0.cpu().numpy()
+        out[1:] = rest.cpu().numpy()
+        return out
+
+    @staticmethod
+    def _st(state):
+        s0, rest = state
+        return _abi.HeomState(s0.data_ptr(), rest.data_ptr() if rest.numel() else None)
+
+    # ---------------------------------------------------------------- calls --
+    def tables(self):
+        """(tuples uint8 [n][W], plus int32 [n][W], minus int32 [n][W], level uint8 [n])."""
+        n, W = self.n_ado, max(self.W, 1)
+        t = np.zeros((n, W), np.uint8)
+        p = np.zeros((n, W), np.int32)
+        m = np.zeros((n, W), np.int32)
+        lev = np.zeros(n, np.uint8)
+        check(load().heom_copy_tables(self.handle, t.ctypes.data, p.ctypes.data, m.ctypes.data,
+                                      lev.ctypes.data, _stream_handle()))
+        return t[:, :self.W], p[:, :self.W], m[:, :self.W], lev
+
+    def coefficients(self):
+        W, N = max(self.W, 1), self.N
+        g, c, ln, ds = np.zeros(W), np.zeros(W), np.zeros(W), np.zeros(N)
+        check(load().heom_coefficients(self.handle, g.ctypes.data, c.ctypes.data, ln.ctypes.data,
+                                       ds.ctypes.data))
+        return g[:self.W], c[:self.W], ln[:self.W], ds
+
+    def rhs(self, state_in, state_out, hermitian=False, stream=None):
+        check(load().heom_rhs(self.handle, self._st(state_in), self._st(state_out),
+                              1 if hermitian else 0, _stream_handle(stream)))
+
+    def work_bytes(self, n_steps, record_every, kind):
+        info = _info_struct(self.info)
+        return load().heom_propagate_work_bytes(ctypes.byref(info), n_steps, record_every, kind)
+
+    def workspace(self, n_steps, record_every, kind):
+        torch = _torch()
+        return torch.empty(self.work_bytes(n_steps, record_every, kind), dtype=torch.uint8,
+                           device="cuda")
+
+    def propagate(self, state, dt_fs, n_steps, record_every=1, observable=None, hermitian=False,
+                  work=None, stream=None, want_records=True):
+        """heom_propagate; returns the records [n_rec, record_doubles] (numpy)."""
+        obs = observable or {"kind": "population"}
+        kind = OBS_POPULATION if obs["kind"] == "population" else OBS_DIPOLE
+        mu = np.ascontiguousarray(obs.get("mu", np.zeros(self.N)), dtype=np.float64)
+        o = _abi.HeomObservable(kind, int(obs.get("ground", 0)),
+                                mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        if work is None:
+            work = self.workspace(n_steps, record_every, kind)
+        n_rec = load().heom_record_count(n_steps, record_every)
+        rd = load().heom_record_doubles(self.N, kind)
+        rec = np.zeros((n_rec, rd)) if want_records else None
+        check(load().heom_propagate(self.handle, self._st(state), ctypes.c_void_p(work.data_ptr()),
+                                    work.numel(), float(dt_fs), int(n_steps), int(record_every),
+                                    ctypes.byref(o), 1 if hermitian else 0,
+                                    rec.ctypes.data if rec is not None else None,
+                                    _stream_handle(stream)))
+        return rec
+
+    def get_state(self, state):
+        s0, rest = state
+        h0 = np.zeros((self.N, self.N), np.complex128)
+        hr = np.zeros(tuple(rest.shape), np.complex128 if self.precision == FP64 else np.complex64)
+        check(load().heom_get_state(self.handle, self._st(state), h0.ctypes.data,
+                                    hr.ctypes.data if hr.size else None, _stream_handle()))
+        return h0, hr
+
+    def set_state(self, state, host_sigma0, host_rest):
+        h0 = np.ascontiguousarray(host_sigma0, dtype=np.complex128)
+        hr = np.ascontiguousarray(host_rest, dtype=np.complex128 if self.precision == FP64
+                                  else np.complex64)
+        check(load().heom_set_state(self.handle, self._st(state), h0.ctypes.data,
+                                    hr.ctypes.data if hr.size else None, _stream_handle()))

@@ -1,0 +1,78 @@
+// Internal descriptors shared by the host runtime and the gfx950 kernels.
+// Not part of the C ABI (include/heom.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace heom {
+
+constexpr int kMaxStates = 64;
+constexpr int kBlock = 256;
+
+// Device pointers into the caller's tables buffer, plus the scalars the
+// kernels need.  Everything here is written once by heom_build_hierarchy.
+struct Tables {
+    int32_t N, W, D, n_ado;
+    int32_t h_complex;            // H has a non-zero imaginary part
+    const double* h_re;           // [N*N] rad/fs, diagonal shifted by -mean(diag)
+    const double* h_im;           // [N*N]
+    const int32_t* mode_site;     // [W]
+    const double* mode_gamma;     // [W] 1/fs
+    const double* mode_c;         // [W] rad/fs^2 (times the gauge sign)
+    const double* mode_lamnu;     // [W] lambda*nu for k = 0 (times the gauge sign)
+    const double* plus_coef;      // [W][D+1]: sign * sqrt((n+1)|c_l|)
+    const double* minus_coef;     // [W][D+1]: sqrt(n/|c_l|)
+    const double* delta_state;    // [N] correction coefficient summed per state
+    const int32_t* state_mode_begin;  // [N+1]
+    const int32_t* state_modes;       // [W] modes grouped by coupled state
+    const int64_t* binom;         // [(D+2)][(W+1)]: C(m+k, k), saturating
+    uint8_t* tuples;              // [n_ado][W]
+    uint8_t* level;               // [n_ado]
+    int32_t* plus;                // [n_ado][W], -1 = absent
+    int32_t* minus;               // [n_ado][W], -1 = absent
+    double* damping;              // [n_ado]: sum_l n_l gamma_l
+};
+
+// One propagation (or one right-hand-side evaluation) as the kernels see it.
+// Array slot 0 is the caller's state; slots 1..3 are RK4 stage copies.
+struct Job {
+    Tables t;
+    void* sig0[4];                // complex128 [N][N]
+    void* rest[4];                // [n_ado-1][N][N], complex128 or complex64
+    double dt;
+    int32_t herm;                 // every ADO is Hermitian
+    int32_t tile_begin;           // first bulk tile of this job in a batched launch
+    int32_t n_tiles;              // bulk tiles of this job
+    int32_t ados_per_tile;
+    double* records;              // [n_rec_max][rec_doubles]
+    const double* mu;             // [N] (dipole observable)
+    int64_t* step;                // device step counter
+    int32_t* status;              // device status word (1 = non-finite observable)
+    int64_t n_rec_max;
+    int32_t rec_every, rec_kind, rec_doubles, ground;
+};
+
+// What one RK4 stage launch reads and writes:
+//   out = w_in * in + sum_m wbase[m] * base[m] + hmul * dt * f(in)
+struct StageSpec {
+    int32_t in, out;
+    int32_t nbase;
+    int32_t base[3];
+    double wbase[3];
+    double w_in;
+    double hmul;
+    int32_t record_initial;  // record sigma_0 of `in` when the step counter is 0
+    int32_t record_after;    // advance the step counter, record the output
+};
+
+// Kernel launchers (heom_kernels.hip).  All enqueue on `stream` and return the
+// HIP error of the launch.
+hipError_t launch_enumerate(const Tables& t, hipStream_t stream);
+hipError_t launch_stage(const Job& single, const Job* jobs_dev, int n_jobs, int total_tiles,
+                        int precision, const StageSpec& sp, hipStream_t stream);
+int bulk_ados_per_tile(int N);
+
+}  // namespace heom
