@@ -1,0 +1,185 @@
+"""Benchmark of the HEOM RK4 hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision P]
+
+One step is one classic RK4 step (four right-hand-side evaluations over every
+ADO, fused into four stage launches).  The default workload is the 48-site
+aggregate (W = 96 modes, depth 3, 156849 ADOs of 48x48, FP32 bulk with FP64
+sigma_0 and observables), the largest configuration and the one whose working
+set (about 15 GB) is bound by HBM bandwidth.  Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import heom_inputs as hi  # noqa: E402
+
+METRIC = "HEOM ADO-updates/s + HBM GB/s; serve p50/p99 latency vs plain FP64"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "aggregate48": lambda: hi.aggregate48(),
+    "aggregate24": lambda: hi.aggregate24(),
+    "fmo_like": lambda: hi.fmo_like(),
+    "dimer": lambda: hi.dimer(),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="aggregate48", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp32_mixed", choices=["fp32_mixed", "fp64"])
+    ap.add_argument("--cpu-baseline-seconds", type=float, default=10.0,
+                    help="target CPU time of the oracle sample (0 disables it)")
+    return ap.parse_args()
+
+
+def cpu_baseline(prob, target_s):
+    """Time the FP64 oracle on a bounded sample of the same workload: the
+    right-hand side of a contiguous block of the deepest ADOs (the level that
+    holds most of the hierarchy), single-threaded on this host.  One
+    ADO-update is four right-hand-side evaluations."""
+    import oracle
+    W, n = oracle.sizes(prob)
+    N = prob["H"].shape[0]
+    x = np.zeros((n, N, N), np.complex128)  # pages are touched only where read
+    x[0] = prob["rho0"]
+    t0 = time.perf_counter()
+    oracle.rhs(prob, x, 0, 0)  # model and table construction only
+    t_setup = time.perf_counter() - t0
+    k = 1
+    while True:
+        t0 = time.perf_counter()
+        oracle.rhs(prob, x, n - k, n)
+        dt = time.perf_counter() - t0 - t_setup
+        if dt * 2 > target_s or k >= n:
+            break
+        k = min(n, max(k * 2, int(k * target_s / max(dt, 1e-3) * 0.6)))
+    per_rhs = max(dt, 1e-9) / k
+    return {"value": 1.0 / (4.0 * per_rhs), "unit": "ADO-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "FP64 oracle right-hand side of the last %d ADOs (depth-%d level) of %s, "
+                      "%.1f s of CPU; one ADO-update = 4 evaluations; model setup (%.1f s) "
+                      "excluded; host %s" % (k, prob["depth"], prob.get("name", "?"), dt, t_setup,
+                                             platform.processor() or platform.machine())}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1803_03498_amd as heom
+    from paper_1803_03498_amd import _abi
+
+    prob = WORKLOADS[args.workload]()
+    precision = heom.FP32_MIXED if args.precision == "fp32_mixed" else heom.FP64
+    steps = args.steps if args.steps is not None else (50 if args.workload == "aggregate48" else 200)
+    warmup = args.warmup if args.warmup is not None else 5
+    torch.cuda.set_device(0)
+    h = heom.Hierarchy(prob, precision)
+    N, n = h.N, h.n_ado
+    info = h.info
+    rec_every = prob["record_every"]
+    st = h.new_state(prob["rho0"])
+    work = h.workspace(max(steps, warmup), rec_every, heom.OBS_POPULATION)
+    print("workload %s: N=%d W=%d D=%d n_ado=%d precision=%s state=%.2f GB" % (
+        args.workload, N, h.W, prob["depth"], n, args.precision,
+        (info["rest_bytes"] + info["sigma0_bytes"]) / 1e9), file=sys.stderr, flush=True)
+
+    lib = heom.load()
+    h.propagate(st, prob["dt_fs"], warmup, rec_every, hermitian=True, work=work)
+    torch.cuda.synchronize()
+    lib.heom_timing_enable(1)
+    lib.heom_timing_read(None, None, None, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rec = h.propagate(st, prob["dt_fs"], steps, rec_every, hermitian=True, work=work)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lib.heom_timing_enable(0)
+    ms = ctypes.c_double()
+    launches = ctypes.c_int64()
+    kbytes = ctypes.c_double()
+    lib.heom_timing_read(ctypes.byref(ms), ctypes.byref(launches), ctypes.byref(kbytes), 1)
+
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / steps
+    ado_updates = n * steps / elapsed
+    e = info["elem_bytes"]
+    step_bytes = 13.0 * ((n - 1) * N * N * e + N * N * 16)
+    hbm_gbs = step_bytes * steps / elapsed / 1e9
+    avg_launch_s = ms.value / 1e3 / max(launches.value, 1)
+    bytes_per_launch = kbytes.value / max(launches.value, 1)
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    pops = rec[-1, :N]
+    print("ms/step %.3f  ADO-updates/s %.3e  alg HBM %.0f GB/s  bulk kernel avg %.3f ms "
+          "(%.0f GB/s)  trace %.15f" % (ms_per_step, ado_updates, hbm_gbs, avg_launch_s * 1e3,
+                                        achieved, rec[-1, N]), file=sys.stderr, flush=True)
+    if not np.all(np.isfinite(pops)):
+        raise RuntimeError("non-finite populations")
+
+    cpu = None
+    if args.cpu_baseline_seconds > 0:
+        cpu = cpu_baseline(prob, args.cpu_baseline_seconds)
+
+    line = {
+        "metric": METRIC,
+        "value": ado_updates,
+        "unit": "ADO-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if precision == heom.FP32_MIXED else "f64",
+        "data": "synthetic",
+        "hbm_GBps_algorithmic": hbm_gbs,
+        "config": {
+            "workload": "%s: %d sites, W=%d modes, depth %d, %d ADOs of %dx%d %s; RK4 dt=%g fs"
+                        % (args.workload, N, h.W, prob["depth"], n, N, N,
+                           "complex64 (sigma_0 complex128)" if precision == heom.FP32_MIXED
+                           else "complex128", prob["dt_fs"]),
+            "n_ado": n, "n_states": N, "n_modes": h.W, "depth": prob["depth"],
+            "precision": args.precision, "record_every": rec_every,
+            "bytes_per_step_algorithmic": step_bytes,
+        },
+        "roofline": {
+            "kernel": "k_bulk_fma (RK4 stage, ADOs u>=1)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_ms": avg_launch_s * 1e3,
+            "bytes_per_launch_algorithmic": bytes_per_launch,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

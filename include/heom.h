@@ -209,6 +209,70 @@ heom_status heom_set_state(const heom_hierarchy* h, heom_state s, const void* ho
 /* Release a handle (does not touch caller memory). */
 heom_status heom_destroy(heom_hierarchy* h);
 
+/* Kernel timing, for benchmarks (process-wide, off by default).  While
+ * enabled, heom_propagate brackets every launch of the bulk RK4 stage kernel
+ * (ADOs u >= 1) with a pair of HIP events recorded on the caller's stream and,
+ * after its final synchronisation, adds their elapsed times.  heom_timing_read
+ * returns the accumulated milliseconds, the number of launches and the
+ * algorithmic bytes those launches move (per RK4 step: 13 passes over the
+ * ADO array, i.e. 2/3/3/5 passes for stages 1..4; neighbour reads counted
+ * once), and optionally resets the counters. */
+heom_status heom_timing_enable(int32_t enable);
+heom_status heom_timing_read(double* bulk_ms, int64_t* bulk_launches, double* bulk_bytes,
+                             int32_t reset);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of independent propagations.                  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct heom_server heom_server;
+
+/* A propagation request: a problem, its step count and observable, and n_runs
+ * initial states that share the problem (e.g. three dipole directions of a
+ * linear-absorption run).  rho0 is host complex128 [n_runs][N][N]; every other
+ * ADO starts at zero.  obs.mu is [n_runs][N] for HEOM_OBS_DIPOLE. */
+typedef struct {
+    heom_problem problem;
+    int32_t n_runs;         /* 1..8                                   */
+    int32_t record_every;   /* >= 1                                   */
+    int64_t n_steps;        /* >= 1                                   */
+    double dt_fs;
+    const double* rho0;     /* host complex128 [n_runs][N][N]         */
+    heom_observable obs;    /* mu: [n_runs][N] for dipole runs        */
+    int32_t hermitian;      /* the initial state is Hermitian         */
+} heom_request;
+
+typedef struct {
+    heom_status status;     /* HEOM_OK, HEOM_PENDING or an error       */
+    int64_t n_records;      /* per run                                 */
+    int32_t record_doubles; /* doubles per record                      */
+    const double* records;  /* [n_runs][n_records][record_doubles], owned by
+                               the server until heom_release          */
+    double t_submit_s;      /* host monotonic clock, seconds           */
+    double t_admit_s;
+    double t_finish_s;
+} heom_result;
+
+/* Create a server on one device stream.  arena_dev/arena_bytes is caller-owned
+ * device memory that the server sub-allocates for tables, states, workspaces
+ * and records of admitted requests; max_active bounds the requests resident
+ * at once.  A scheduler thread owns the stream until heom_server_destroy. */
+heom_status heom_server_create(void* arena_dev, size_t arena_bytes, int32_t max_active,
+                               void* stream, heom_server** out);
+/* Thread-safe.  Copies the request; HEOM_E_NOMEM if it can never fit the
+ * arena, HEOM_E_INVAL / HEOM_E_RANGE as heom_plan. */
+heom_status heom_submit(heom_server* s, const heom_request* req, uint64_t* ticket);
+/* Thread-safe.  HEOM_PENDING until the request finished; then its status. */
+heom_status heom_poll(heom_server* s, uint64_t ticket, heom_result* out);
+/* Thread-safe: block until the request finished (timeout_s < 0: no limit). */
+heom_status heom_wait(heom_server* s, uint64_t ticket, double timeout_s, heom_result* out);
+/* Thread-safe: cancel a queued or running request. */
+heom_status heom_cancel(heom_server* s, uint64_t ticket);
+/* Thread-safe: free the result of a finished request. */
+heom_status heom_release(heom_server* s, uint64_t ticket);
+/* Stop the scheduler (running requests are cancelled) and free the server. */
+heom_status heom_server_destroy(heom_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -151,7 +151,7 @@ def rhs(prob, state, u_begin=0, u_end=-1):
     """One evaluation of eq. (HEOM); state is complex128 [n_ado][N][N]."""
     pk = _Packed(prob)
     x = np.ascontiguousarray(state, dtype=np.complex128)
-    out = np.zeros_like(x)
+    out = np.zeros(x.shape, np.complex128)  # calloc: untouched pages stay unmapped
     if lib().orc_rhs(ctypes.byref(pk.s), x.ctypes.data, out.ctypes.data, u_begin, u_end):
         raise ValueError("invalid problem")
     return out

@@ -18,7 +18,7 @@ from . import _abi
 from ._abi import FP32_MIXED, FP64, OBS_DIPOLE, OBS_POPULATION, HeomError, check, load
 
 __all__ = ["FP64", "FP32_MIXED", "OBS_POPULATION", "OBS_DIPOLE", "HeomError", "Problem", "plan",
-           "Hierarchy", "load"]
+           "Hierarchy", "Server", "load"]
 
 
 def _torch():
@@ -203,3 +203,85 @@ class Hierarchy:
                                   else np.complex64)
         check(load().heom_set_state(self.handle, self._st(state), h0.ctypes.data,
                                     hr.ctypes.data if hr.size else None, _stream_handle()))
+
+
+class Server:
+    """Continuous-batching server (heom_server_create / heom_submit / heom_poll).
+
+    The arena is one caller-owned device buffer; the library sub-allocates
+    tables, states, workspaces and records of admitted requests from it."""
+
+    def __init__(self, arena_bytes, max_active, stream=None):
+        torch = _torch()
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
+        self._stream = stream
+        h = ctypes.c_void_p()
+        check(load().heom_server_create(ctypes.c_void_p(self.arena.data_ptr()), int(arena_bytes),
+                                        int(max_active), _stream_handle(stream), ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, runs, precision=FP32_MIXED, hermitian=None):
+        """Submit runs (list of run dicts sharing one problem, see heom_inputs)
+        as one request; returns its ticket."""
+        r0 = runs[0]
+        prob = Problem(r0, precision)
+        N = prob.N
+        kind = OBS_POPULATION if r0["observable"]["kind"] == "population" else OBS_DIPOLE
+        rho0 = np.ascontiguousarray(np.stack([np.asarray(r["rho0"], np.complex128) for r in runs]))
+        mu = np.ascontiguousarray(np.stack([np.asarray(r["observable"].get("mu", np.zeros(N)),
+                                                       np.float64) for r in runs]))
+        if hermitian is None:
+            hermitian = kind == OBS_POPULATION
+        dp = ctypes.POINTER(ctypes.c_double)
+        req = _abi.HeomRequest(prob.struct, len(runs), int(r0["record_every"]), int(r0["n_steps"]),
+                               float(r0["dt_fs"]), rho0.ctypes.data_as(dp),
+                               _abi.HeomObservable(kind, int(r0["observable"].get("ground", 0)),
+                                                   mu.ctypes.data_as(dp)),
+                               1 if hermitian else 0)
+        t = ctypes.c_uint64()
+        check(load().heom_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
+        self._keep[t.value] = len(runs)
+        return t.value
+
+    def _result(self, ticket, res, status):
+        n_runs = self._keep.get(ticket, 1)
+        out = {"status": status, "t_submit": res.t_submit_s, "t_admit": res.t_admit_s,
+               "t_finish": res.t_finish_s, "records": None}
+        if status == _abi.HEOM_OK and res.records:
+            n = n_runs * res.n_records * res.record_doubles
+            arr = np.ctypeslib.as_array(res.records, shape=(n,)).copy()
+            out["records"] = arr.reshape(n_runs, res.n_records, res.record_doubles)
+        return out
+
+    def poll(self, ticket):
+        res = _abi.HeomResult()
+        st = load().heom_poll(self.handle, ticket, ctypes.byref(res))
+        if st == -7:
+            check(st)
+        return self._result(ticket, res, st)
+
+    def wait(self, ticket, timeout_s=-1.0):
+        res = _abi.HeomResult()
+        st = load().heom_wait(self.handle, ticket, float(timeout_s), ctypes.byref(res))
+        if st == -7:
+            check(st)
+        return self._result(ticket, res, st)
+
+    def cancel(self, ticket):
+        check(load().heom_cancel(self.handle, ticket))
+
+    def release(self, ticket):
+        check(load().heom_release(self.handle, ticket))
+        self._keep.pop(ticket, None)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load().heom_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -86,6 +86,15 @@ SIGNATURES = {
     "heom_get_state": (i32, [vp, HeomState, vp, vp, vp]),
     "heom_set_state": (i32, [vp, HeomState, vp, vp, vp]),
     "heom_destroy": (i32, [vp]),
+    "heom_timing_enable": (i32, [i32]),
+    "heom_timing_read": (i32, [P(f64), P(i64), P(f64), i32]),
+    "heom_server_create": (i32, [vp, sz, i32, vp, P(vp)]),
+    "heom_submit": (i32, [vp, P(HeomRequest), P(u64)]),
+    "heom_poll": (i32, [vp, u64, P(HeomResult)]),
+    "heom_wait": (i32, [vp, u64, f64, P(HeomResult)]),
+    "heom_cancel": (i32, [vp, u64]),
+    "heom_release": (i32, [vp, u64]),
+    "heom_server_destroy": (i32, [vp]),
 }
 
 _lib = None

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libheom.so")
-SOURCES = [os.path.join(CSRC, "heom_kernels.hip"), os.path.join(CSRC, "heom_host.cpp")]
+SOURCES = [os.path.join(CSRC, "heom_kernels.hip"), os.path.join(CSRC, "heom_host.cpp"),
+           os.path.join(CSRC, "heom_server.cpp")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

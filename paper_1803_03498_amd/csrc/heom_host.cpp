@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -464,6 +466,14 @@ heom_status heom_coefficients(const heom_hierarchy* h, double* gamma, double* c,
 
 namespace {
 
+struct TimingState {
+    std::atomic<bool> enabled{false};
+    std::mutex mu;
+    double ms = 0.0, bytes = 0.0;
+    int64_t launches = 0;
+};
+TimingState g_timing;
+
 heom::Job base_job(const heom_hierarchy* h) {
     heom::Job j{};
     j.t = h->t;
@@ -476,6 +486,85 @@ heom::Job base_job(const heom_hierarchy* h) {
 }
 
 bool aligned(const void* p) { return reinterpret_cast<uintptr_t>(p) % 256 == 0; }
+
+}  // namespace
+
+namespace heom {
+
+const Tables& hierarchy_tables(const heom_hierarchy* h) { return h->t; }
+int hierarchy_precision(const heom_hierarchy* h) { return h->d.precision; }
+double hierarchy_rate_bound(const heom_hierarchy* h) { return h->d.rate_bound; }
+Job hierarchy_job(const heom_hierarchy* h) { return base_job(h); }
+const heom_info& hierarchy_info(const heom_hierarchy* h) { return h->info; }
+
+size_t control_bytes(int N) { return 1024 + align256((size_t)N * 8); }
+
+// Workspace layout: [step @0, status @256, mu @1024][three stage copies][records].
+Job bind_workspace(const heom_hierarchy* h, heom_state io, char* w, double dt, int64_t n_steps,
+                   int record_every, int kind, int ground, int hermitian) {
+    Job j = base_job(h);
+    const int N = h->t.N;
+    j.herm = hermitian ? 1 : 0;
+    j.dt = dt;
+    j.step = reinterpret_cast<int64_t*>(w);
+    j.status = reinterpret_cast<int32_t*>(w + 256);
+    j.mu = reinterpret_cast<double*>(w + 1024);
+    size_t off = control_bytes(N);
+    for (int k = 1; k <= 3; ++k) {
+        j.sig0[k] = w + off;
+        off += align256(h->info.sigma0_bytes);
+        j.rest[k] = w + off;
+        off += align256(std::max<size_t>(h->info.rest_bytes, 1));
+    }
+    j.sig0[0] = io.sigma0;
+    j.rest[0] = io.rest;
+    j.records = reinterpret_cast<double*>(w + off);
+    j.n_rec_max = heom_record_count(n_steps, record_every);
+    j.rec_every = record_every;
+    j.rec_kind = kind;
+    j.rec_doubles = heom_record_doubles(N, kind);
+    j.ground = ground;
+    return j;
+}
+
+heom_status problem_rate_bound(const heom_problem* p, double* rate) {
+    Derived d;
+    heom_status s = derive(p, d);
+    if (s == HEOM_OK) *rate = d.rate_bound;
+    return s;
+}
+
+double rk4_real_limit() { return kRk4RealLimit; }
+
+void set_last_error(const std::string& msg) { g_error = msg; }
+
+double monotonic_seconds() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+void rk4_stage_specs(StageSpec sp[4]) {
+    for (int k = 0; k < 4; ++k) sp[k] = StageSpec{};
+    // Y2 = y + dt/2 f(y)
+    sp[0].in = 0; sp[0].out = 1; sp[0].w_in = 1.0; sp[0].hmul = 0.5; sp[0].record_initial = 1;
+    // Y3 = y + dt/2 f(Y2)
+    sp[1].in = 1; sp[1].out = 2; sp[1].nbase = 1; sp[1].base[0] = 0; sp[1].wbase[0] = 1.0;
+    sp[1].hmul = 0.5;
+    // Y4 = y + dt f(Y3)
+    sp[2].in = 2; sp[2].out = 3; sp[2].nbase = 1; sp[2].base[0] = 0; sp[2].wbase[0] = 1.0;
+    sp[2].hmul = 1.0;
+    // y' = (-y + Y2 + 2 Y3 + Y4)/3 + dt/6 f(Y4): the textbook y + dt/6 (k1 + 2k2 + 2k3 + k4)
+    // with k1 = 2(Y2 - y)/dt, k2 = 2(Y3 - y)/dt, k3 = (Y4 - y)/dt
+    sp[3].in = 3; sp[3].out = 0; sp[3].w_in = 1.0 / 3.0; sp[3].nbase = 3;
+    sp[3].base[0] = 0; sp[3].wbase[0] = -1.0 / 3.0;
+    sp[3].base[1] = 1; sp[3].wbase[1] = 1.0 / 3.0;
+    sp[3].base[2] = 2; sp[3].wbase[2] = 2.0 / 3.0;
+    sp[3].hmul = 1.0 / 6.0; sp[3].record_after = 1;
+}
+
+}  // namespace heom
+
+namespace {
 
 heom_status check_state(const heom_hierarchy* h, const heom_state& s, const char* what) {
     if (!s.sigma0) return fail(HEOM_E_INVAL, "%s.sigma0 is NULL", what);
@@ -537,55 +626,31 @@ heom_status heom_propagate(const heom_hierarchy* h, heom_state io, void* work_de
     const int rd = heom_record_doubles(N, kind);
     const int64_t n_rec = heom_record_count(n_steps, record_every);
     char* w = static_cast<char*>(work_dev);
-    heom::Job j = base_job(h);
-    j.herm = hermitian ? 1 : 0;
-    j.dt = dt_fs;
-    j.step = reinterpret_cast<int64_t*>(w);
-    j.status = reinterpret_cast<int32_t*>(w + 256);
-    double* mu_dev = reinterpret_cast<double*>(w + 1024);
-    size_t off = 1024 + align256(N * 8);
-    for (int k = 1; k <= 3; ++k) {
-        j.sig0[k] = w + off;
-        off += align256(h->info.sigma0_bytes);
-        j.rest[k] = w + off;
-        off += align256(std::max<size_t>(h->info.rest_bytes, 1));
-    }
-    j.sig0[0] = io.sigma0;
-    j.rest[0] = io.rest;
-    j.records = reinterpret_cast<double*>(w + off);
-    j.n_rec_max = n_rec;
-    j.rec_every = record_every;
-    j.rec_kind = kind;
-    j.rec_doubles = rd;
-    j.ground = kind == HEOM_OBS_DIPOLE ? obs->ground : 0;
-    j.mu = mu_dev;
+    heom::Job j = heom::bind_workspace(h, io, w, dt_fs, n_steps, record_every, kind,
+                                       kind == HEOM_OBS_DIPOLE ? obs->ground : 0, hermitian);
 
     hipStream_t st = static_cast<hipStream_t>(stream);
     // control block: step = 0, status = 0, mu
-    std::vector<char> ctl(1024 + align256(N * 8), 0);
+    std::vector<char> ctl(heom::control_bytes(N), 0);
     if (kind == HEOM_OBS_DIPOLE) std::memcpy(ctl.data() + 1024, obs->mu, N * 8);
     HIP_TRY(hipMemcpyAsync(w, ctl.data(), ctl.size(), hipMemcpyHostToDevice, st));
 
-    heom::StageSpec sp[4] = {};
-    // Y2 = y + dt/2 f(y)
-    sp[0].in = 0; sp[0].out = 1; sp[0].w_in = 1.0; sp[0].hmul = 0.5; sp[0].record_initial = 1;
-    // Y3 = y + dt/2 f(Y2)
-    sp[1].in = 1; sp[1].out = 2; sp[1].nbase = 1; sp[1].base[0] = 0; sp[1].wbase[0] = 1.0;
-    sp[1].hmul = 0.5;
-    // Y4 = y + dt f(Y3)
-    sp[2].in = 2; sp[2].out = 3; sp[2].nbase = 1; sp[2].base[0] = 0; sp[2].wbase[0] = 1.0;
-    sp[2].hmul = 1.0;
-    // y' = (-y + Y2 + 2 Y3 + Y4)/3 + dt/6 f(Y4)
-    sp[3].in = 3; sp[3].out = 0; sp[3].w_in = 1.0 / 3.0; sp[3].nbase = 3;
-    sp[3].base[0] = 0; sp[3].wbase[0] = -1.0 / 3.0;
-    sp[3].base[1] = 1; sp[3].wbase[1] = 1.0 / 3.0;
-    sp[3].base[2] = 2; sp[3].wbase[2] = 2.0 / 3.0;
-    sp[3].hmul = 1.0 / 6.0; sp[3].record_after = 1;
+    heom::StageSpec sp[4];
+    heom::rk4_stage_specs(sp);
 
     const int tiles = h->t.n_ado > 1 ? j.n_tiles : 0;
+    const bool timed = g_timing.enabled.load() && tiles > 0;
+    std::vector<hipEvent_t> ev;
+    if (timed) {
+        ev.resize(2 * (size_t)n_steps * 4);
+        for (auto& x : ev) HIP_TRY(hipEventCreate(&x));
+    }
+    static const int kPasses[4] = {2, 3, 3, 5};
     for (int64_t step = 0; step < n_steps; ++step) {
         for (int k = 0; k < 4; ++k) {
-            hipError_t e = heom::launch_stage(j, nullptr, 0, tiles, h->d.precision, sp[k], st);
+            hipError_t e = heom::launch_stage(j, nullptr, 0, tiles, h->d.precision, sp[k], st,
+                                              timed ? ev[2 * (step * 4 + k)] : nullptr,
+                                              timed ? ev[2 * (step * 4 + k) + 1] : nullptr);
             if (e != hipSuccess) return fail(HEOM_E_DEVICE, "stage launch: %s", hipGetErrorString(e));
         }
     }
@@ -599,7 +664,42 @@ heom_status heom_propagate(const heom_hierarchy* h, heom_state io, void* work_de
     if (host_out)
         HIP_TRY(hipMemcpyAsync(host_out, j.records, (size_t)n_rec * rd * 8, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    if (timed) {
+        double ms_total = 0.0, bytes = 0.0;
+        const double pass = (double)h->info.rest_bytes;
+        for (int64_t step = 0; step < n_steps; ++step)
+            for (int k = 0; k < 4; ++k) {
+                float ms = 0.0f;
+                HIP_TRY(hipEventElapsedTime(&ms, ev[2 * (step * 4 + k)], ev[2 * (step * 4 + k) + 1]));
+                ms_total += ms;
+                bytes += kPasses[k] * pass;
+            }
+        for (auto& x : ev) (void)hipEventDestroy(x);
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        g_timing.ms += ms_total;
+        g_timing.launches += 4 * n_steps;
+        g_timing.bytes += bytes;
+    }
     if (status) return fail(HEOM_E_NUMERIC, "non-finite observable");
+    return HEOM_OK;
+}
+
+heom_status heom_timing_enable(int32_t enable) {
+    g_timing.enabled.store(enable != 0);
+    return HEOM_OK;
+}
+
+heom_status heom_timing_read(double* bulk_ms, int64_t* bulk_launches, double* bulk_bytes,
+                             int32_t reset) {
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    if (bulk_ms) *bulk_ms = g_timing.ms;
+    if (bulk_launches) *bulk_launches = g_timing.launches;
+    if (bulk_bytes) *bulk_bytes = g_timing.bytes;
+    if (reset) {
+        g_timing.ms = 0.0;
+        g_timing.launches = 0;
+        g_timing.bytes = 0.0;
+    }
     return HEOM_OK;
 }
 

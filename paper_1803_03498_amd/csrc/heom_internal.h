@@ -6,6 +6,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 namespace heom {
 
@@ -71,8 +72,33 @@ struct StageSpec {
 // Kernel launchers (heom_kernels.hip).  All enqueue on `stream` and return the
 // HIP error of the launch.
 hipError_t launch_enumerate(const Tables& t, hipStream_t stream);
+// ev_begin/ev_end (may be null) bracket the bulk-kernel launch.
 hipError_t launch_stage(const Job& single, const Job* jobs_dev, int n_jobs, int total_tiles,
-                        int precision, const StageSpec& sp, hipStream_t stream);
+                        int precision, const StageSpec& sp, hipStream_t stream,
+                        hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
 int bulk_ados_per_tile(int N);
+// Which bulk kernel a job uses: 0 = FMA path, otherwise 16*nb >= N on the MFMA path.
+int bulk_mfma_blocks(int N, bool h_complex, int precision);
 
+}  // namespace heom
+
+#include "heom.h"
+
+namespace heom {
+// Host-side accessors of a built hierarchy (heom_host.cpp), for the server.
+const Tables& hierarchy_tables(const heom_hierarchy* h);
+int hierarchy_precision(const heom_hierarchy* h);
+double hierarchy_rate_bound(const heom_hierarchy* h);
+Job hierarchy_job(const heom_hierarchy* h);       // job with tables, tiles and sizes set
+const heom_info& hierarchy_info(const heom_hierarchy* h);
+size_t control_bytes(int N);
+// Point a job at a caller state (slot 0) and a propagation workspace of
+// heom_propagate_work_bytes bytes (stage copies, control block, records).
+Job bind_workspace(const heom_hierarchy* h, heom_state io, char* work, double dt,
+                   int64_t n_steps, int record_every, int kind, int ground, int hermitian);
+heom_status problem_rate_bound(const heom_problem* p, double* rate);
+double rk4_real_limit();
+void set_last_error(const std::string& msg);
+void rk4_stage_specs(StageSpec sp[4]);           // the four classic RK4 stages
+double monotonic_seconds();
 }  // namespace heom

@@ -7,6 +7,8 @@
 // superoperator masks that follow it, and the ADO rescaling substitution).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "heom_internal.h"
 
 namespace heom {
@@ -269,36 +271,43 @@ __device__ void record_sigma0(const Job& J, const double* sS, int64_t slot) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int n_jobs,
                                                 StageSpec sp) {
+    constexpr int EPT = kMaxStates * kMaxStates / kBlock;  // 16 elements per thread at N = 64
     const Job& J = (jobs == nullptr) ? single : jobs[blockIdx.x];
     const Tables& t = J.t;
-    const int N = t.N, NN = N * N;
+    const int N = t.N, NN = N * N, W = t.W, D = t.D;
     extern __shared__ double smem0[];
-    double* sH = smem0;           // 2*NN
-    double* sS = smem0 + 2 * NN;  // 2*NN
+    double* sH = smem0;                 // 2*NN
+    double* sS = smem0 + 2 * NN;        // 2*NN
+    double* sPa = sS + 2 * NN;          // W: "+" weight of mode l at n_l = 0
+    double* sDelta = sPa + W;           // N
+    int* sSite = reinterpret_cast<int*>(sDelta + N);  // W
     const int tid = threadIdx.x;
+    const bool hc = t.h_complex != 0;
     for (int e = tid; e < NN; e += blockDim.x) {
         sH[2 * e] = t.h_re[e];
-        sH[2 * e + 1] = t.h_complex ? t.h_im[e] : 0.0;
+        sH[2 * e + 1] = hc ? t.h_im[e] : 0.0;
         const cpx<double> v = ld<double>(J.sig0[sp.in], e);
         sS[2 * e] = v.re;
         sS[2 * e + 1] = v.im;
     }
+    for (int l = tid; l < W; l += blockDim.x) {
+        sPa[l] = (D > 0) ? t.plus_coef[l * (D + 1)] : 0.0;
+        sSite[l] = t.mode_site[l];
+    }
+    for (int s = tid; s < N; s += blockDim.x) sDelta[s] = t.delta_state[s];
     __syncthreads();
     if (sp.record_initial && tid == 0 && *J.step == 0) record_sigma0(J, sS, 0);
-    const NbSrc<T> nbs{J.sig0[sp.in], J.rest[sp.in], N};
-    const double h = sp.hmul * J.dt;
-    // Values of the new sigma_0 are kept in registers until every thread has
-    // read the old tile, then written back to LDS for the observables.
-    double outr[kMaxStates * kMaxStates / kBlock], outi[kMaxStates * kMaxStates / kBlock];
-    int q = 0;
-    for (int e = tid; e < NN; e += blockDim.x, ++q) {
+
+    // -i [H, sigma_0] and the correction line (the damping vanishes at u = 0)
+    double ar[EPT], ai[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int e = tid + q * kBlock;
+        ar[q] = ai[q] = 0.0;
+        if (e >= NN) continue;
         const int i = e / N, j = e - (e / N) * N;
-        // rhs_element<double> reads neighbours through NbSrc<double>; the
-        // level-1 ADOs are stored in T, so evaluate the coupling lines here.
-        cpx<double> f;
-        {
-            // commutator, correction term (damping is zero for u = 0)
-            double cr = 0, ci = 0;
+        double cr = 0, ci = 0;
+        if (hc) {
             for (int k = 0; k < N; ++k) {
                 const double hr = sH[2 * (i * N + k)], hi = sH[2 * (i * N + k) + 1];
                 const double sr = sS[2 * (k * N + j)], si = sS[2 * (k * N + j) + 1];
@@ -307,48 +316,61 @@ __global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int
                 cr += hr * sr - hi * si - (tr * gr - ti * gi);
                 ci += hr * si + hi * sr - (tr * gi + ti * gr);
             }
-            double ar = ci, ai = -cr;
-            const double s_r = sS[2 * (i * N + j)], s_i = sS[2 * (i * N + j) + 1];
-            if (i != j) {
-                const double dl = t.delta_state[i] + t.delta_state[j];
-                ar -= dl * s_r;
-                ai -= dl * s_i;
+        } else {
+            for (int k = 0; k < N; ++k) {
+                const double hik = sH[2 * (i * N + k)], hkj = sH[2 * (k * N + j)];
+                cr += hik * sS[2 * (k * N + j)] - sS[2 * (i * N + k)] * hkj;
+                ci += hik * sS[2 * (k * N + j) + 1] - sS[2 * (i * N + k) + 1] * hkj;
             }
-            if (t.D > 0 && i != j) {
-                for (int pass = 0; pass < 2; ++pass) {
-                    const int s = pass == 0 ? i : j;
-                    const double vx = pass == 0 ? 1.0 : -1.0;
-                    const bool col = pass == 1;
-                    for (int m = t.state_mode_begin[s]; m < t.state_mode_begin[s + 1]; ++m) {
-                        const int l = t.state_modes[m];
-                        const int nb = 1 + l;  // level-1 ADO e_l
-                        cpx<T> x = (J.herm && col) ? cconj(load_nb<T>(nbs, nb, j, i))
-                                                   : load_nb<T>(nbs, nb, i, j);
-                        const double a = t.plus_coef[l * (t.D + 1)] * vx;
-                        ar -= a * (double)x.im;
-                        ai += a * (double)x.re;
-                    }
+        }
+        const double dl = (i != j) ? sDelta[i] + sDelta[j] : 0.0;
+        ar[q] = ci - dl * sS[2 * e];
+        ai[q] = -cr - dl * sS[2 * e + 1];
+    }
+    // "+" couplings to the level-1 ADOs e_l (index 1 + l), stored in T
+    if (D > 0) {
+        const NbSrc<T> nbs{J.sig0[sp.in], J.rest[sp.in], N};
+        for (int l = 0; l < W; ++l) {
+            const int s = sSite[l], nb = 1 + l;
+            const double pa = sPa[l];
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) {
+                const int e = tid + q * kBlock;
+                const int i = e / N, j = e - (e / N) * N;
+                if (e < NN && i != j && (i == s || j == s)) {
+                    const bool col = (j == s);
+                    const cpx<T> x = (J.herm && col) ? cconj(load_nb<T>(nbs, nb, s, i))
+                                                     : load_nb<T>(nbs, nb, i, j);
+                    const double a = col ? -pa : pa;
+                    ar[q] -= a * (double)x.im;
+                    ai[q] += a * (double)x.re;
                 }
             }
-            f = {ar, ai};
         }
+    }
+    // RK4 stage combination in FP64
+    const double h = sp.hmul * J.dt;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int e = tid + q * kBlock;
+        if (e >= NN) continue;
         double yr = sp.w_in * sS[2 * e], yi = sp.w_in * sS[2 * e + 1];
         for (int m = 0; m < sp.nbase; ++m) {
-            const cpx<double> b = ld<double>(J.sig0[sp.base[m]], e);
-            yr += sp.wbase[m] * b.re;
-            yi += sp.wbase[m] * b.im;
+            const cpx<double> bv = ld<double>(J.sig0[sp.base[m]], e);
+            yr += sp.wbase[m] * bv.re;
+            yi += sp.wbase[m] * bv.im;
         }
-        yr += h * f.re;
-        yi += h * f.im;
-        outr[q] = yr;
-        outi[q] = yi;
+        ar[q] = yr + h * ar[q];
+        ai[q] = yi + h * ai[q];
     }
-    __syncthreads();
-    q = 0;
-    for (int e = tid; e < NN; e += blockDim.x, ++q) {
-        st<double>(J.sig0[sp.out], e, cpx<double>{outr[q], outi[q]});
-        sS[2 * e] = outr[q];
-        sS[2 * e + 1] = outi[q];
+    __syncthreads();  // every thread has read the old tile
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int e = tid + q * kBlock;
+        if (e >= NN) continue;
+        st<double>(J.sig0[sp.out], e, cpx<double>{ar[q], ai[q]});
+        sS[2 * e] = ar[q];
+        sS[2 * e + 1] = ai[q];
     }
     if (sp.record_after) {
         __syncthreads();
@@ -410,7 +432,342 @@ __global__ __launch_bounds__(256) void k_bulk_fma(Job single, const Job* jobs, i
     }
 }
 
+// --------------------------------------------------------------------------
+// Bulk stage kernel, MFMA path (16 <= N <= 64, real H): one ADO per workgroup.
+//
+// The commutator is a batched GEMM with the shared H: X = H [Re sigma | Im sigma]
+// (M = K = N, 2N columns) on 16x16x4 matrix cores, H held in registers as the
+// A operand and sigma staged in LDS as separate real and imaginary planes.
+// For a Hermitian sigma, sigma H = (H sigma)^dagger, so -i[H, sigma] =
+// -i (X - X^dagger) needs only X; otherwise Y = sigma H is a second GEMM.
+// The damping, correction and coupling lines are elementwise and are fused
+// with the RK4 stage combination in the same pass.
+//
+// MFMA 16x16x4 operand layout (lane l of a 64-lane wavefront):
+//   A[i][k]: l = i + 16 k        B[k][j]: l = j + 16 k
+//   D[i][j], f32: l = j + 16 (i / 4), item i % 4
+//   D[i][j], f64: l = j + 16 (i % 4), item i / 4
+// --------------------------------------------------------------------------
+template <typename T>
+struct mfma_acc;
+template <>
+struct mfma_acc<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct mfma_acc<double> {
+    typedef double type __attribute__((ext_vector_type(4)));
+};
+
+__device__ __forceinline__ mfma_acc<float>::type mfma16(float a, float b,
+                                                        mfma_acc<float>::type c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ mfma_acc<double>::type mfma16(double a, double b,
+                                                         mfma_acc<double>::type c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Row (inside a 16x16 tile) of output item r held by `lane`.
+template <typename T>
+__device__ __forceinline__ int mfma_row(int lane, int r);
+template <>
+__device__ __forceinline__ int mfma_row<float>(int lane, int r) {
+    return 4 * (lane >> 4) + r;
+}
+template <>
+__device__ __forceinline__ int mfma_row<double>(int lane, int r) {
+    return 4 * r + (lane >> 4);
+}
+
+// Per-block LDS copies of the small per-problem tables, and the per-ADO link
+// description: every mode's "+" neighbour and coefficient, and a compact list
+// of the active "-" links (modes with n_l > 0, at most D of them) in mode
+// order, built with a wave ballot so that the order is deterministic.
+template <typename T>
+struct BlockTables {
+    int32_t* site;   // [W] mode -> coupled state
+    T* delta;        // [N] correction coefficient per state
+    int32_t* pnb;    // [W] "+" neighbour (valid when level < D)
+    T* pa;           // [W] sign * sqrt((n_l+1)|c_l|)
+    int32_t* msite;  // [W] active "-" links: state, neighbour, coefficients
+    int32_t* mnb;
+    T* mml;          // sqrt(n_l/|c_l|) * sign * lambda nu (k = 0)
+    T* mmc;          // sqrt(n_l/|c_l|) * sign * c_l
+    int32_t* count;  // [4] per-wave active counts, [4] = total
+};
+
+template <typename T>
+__device__ __forceinline__ size_t block_tables_bytes(int N, int W) {
+    return (size_t)W * (4 * sizeof(int32_t) + 3 * sizeof(T)) + (size_t)N * sizeof(T) + 8 * 4;
+}
+
+template <typename T>
+__device__ __forceinline__ BlockTables<T> carve_tables(char* p, int N, int W) {
+    BlockTables<T> b;
+    b.pa = reinterpret_cast<T*>(p);
+    b.mml = b.pa + W;
+    b.mmc = b.mml + W;
+    b.delta = b.mmc + W;
+    b.site = reinterpret_cast<int32_t*>(b.delta + N);
+    b.pnb = b.site + W;
+    b.msite = b.pnb + W;
+    b.mnb = b.msite + W;
+    b.count = b.mnb + W;
+    return b;
+}
+
+// Fill the block tables for ADO u (all threads of the block take part;
+// W <= 255 so one pass of 256 threads covers every mode).  Ends with a barrier.
+template <typename T>
+__device__ void fill_block_tables(const Tables& t, int u, int lev, const BlockTables<T>& b) {
+    const int W = t.W, D = t.D, N = t.N;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int s = tid; s < N; s += blockDim.x) b.delta[s] = (T)t.delta_state[s];
+    const int l = tid;
+    int nl = 0;
+    if (l < W) {
+        nl = t.tuples[(size_t)u * W + l];
+        b.site[l] = t.mode_site[l];
+        b.pnb[l] = (lev < D) ? t.plus[(size_t)u * W + l] : -1;
+        b.pa[l] = (T)t.plus_coef[l * (D + 1) + nl];
+    }
+    const bool act = (l < W) && nl > 0;
+    const unsigned long long mask = __ballot(act);
+    if (lane == 0) b.count[wave] = __popcll(mask);
+    __syncthreads();
+    if (act) {
+        int slot = __popcll(mask & ((1ull << lane) - 1));
+        for (int w = 0; w < wave; ++w) slot += b.count[w];
+        const double coef = t.minus_coef[l * (D + 1) + nl];
+        b.msite[slot] = t.mode_site[l];
+        b.mnb[slot] = t.minus[(size_t)u * W + l];
+        b.mml[slot] = (T)(coef * t.mode_lamnu[l]);
+        b.mmc[slot] = (T)(coef * t.mode_c[l]);
+    }
+    if (tid == 0) b.count[4] = b.count[0] + b.count[1] + b.count[2] + b.count[3];
+    __syncthreads();
+}
+
+template <typename T, int NB, bool HERM>
+__global__ __launch_bounds__(256) void k_bulk_mfma(Job single, const Job* jobs, int n_jobs,
+                                                   StageSpec sp) {
+    constexpr int NP = 16 * NB;                           // padded matrix dimension
+    constexpr int LS = NP + 1;                            // LDS row stride (odd: no conflicts
+                                                          // on the transposed reads of X)
+    constexpr int KS = 4 * NB;                            // k-steps of 4 (K = NP)
+    constexpr int NTC = 2 * NB;                           // column tiles of [Re | Im]
+    constexpr int PLANE = NP * LS;
+    constexpr int EPT = (NP * NP + kBlock - 1) / kBlock;  // elements per thread (upper bound)
+    using acc_t = typename mfma_acc<T>::type;
+
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const Job& J = find_job(single, jobs, n_jobs, b);
+    const Tables& t = J.t;
+    const int N = t.N, NN = N * N, W = t.W, D = t.D;
+    const int u = 1 + (b - J.tile_begin);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+
+    extern __shared__ char smem_raw[];
+    T* sSre = reinterpret_cast<T*>(smem_raw);
+    T* sSim = sSre + PLANE;
+    T* sXre = sSim + PLANE;
+    T* sXim = sXre + PLANE;
+    T* sYre = sXim + PLANE;  // general path only
+    T* sYim = sYre + PLANE;
+    const BlockTables<T> bt = carve_tables<T>(reinterpret_cast<char*>(HERM ? sYre : sYim + PLANE),
+                                              N, W);
+
+    // Issue the loads of the own tile and of the stage bases first.
+    const size_t base = (size_t)(u - 1) * NN;
+    const void* in = J.rest[sp.in];
+    cpx<T> own[EPT];
+    cpx<T> acc_base[EPT];
+    int ei[EPT], ej[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int e = tid + q * kBlock;
+        ei[q] = e / N;
+        ej[q] = e - ei[q] * N;
+        own[q] = (e < NN) ? ld<T>(in, base + e) : cpx<T>{(T)0, (T)0};
+        acc_base[q] = {(T)0, (T)0};
+    }
+    for (int m = 0; m < sp.nbase; ++m) {
+        const T w = (T)sp.wbase[m];
+        const void* bp = J.rest[sp.base[m]];
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            if (tid + q * kBlock < NN) {
+                const cpx<T> v = ld<T>(bp, base + tid + q * kBlock);
+                acc_base[q].re += w * v.re;
+                acc_base[q].im += w * v.im;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        if (tid + q * kBlock < NN) {
+            sSre[ei[q] * LS + ej[q]] = own[q].re;
+            sSim[ei[q] * LS + ej[q]] = own[q].im;
+        }
+    }
+    if (N < NP) {
+        for (int idx = tid; idx < NP * NP; idx += kBlock) {
+            const int r = idx / NP, c = idx - (idx / NP) * NP;
+            if (r >= N || c >= N) {
+                sSre[r * LS + c] = (T)0;
+                sSim[r * LS + c] = (T)0;
+            }
+        }
+    }
+    const int lev = t.level[u];
+    const T gam = (T)t.damping[u];
+
+    // H as the A operand: hreg[mt][ks] = H[16 mt + lane%16][4 ks + lane/16]
+    T hreg[NB][KS];
+#pragma unroll
+    for (int mt = 0; mt < NB; ++mt)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int r = 16 * mt + (lane & 15), c = 4 * ks + (lane >> 4);
+            hreg[mt][ks] = (r < N && c < N) ? (T)t.h_re[r * N + c] : (T)0;
+        }
+    const int ksteps = (N + 3) >> 2;
+    fill_block_tables<T>(t, u, lev, bt);  // ends with a barrier (also publishes sS)
+
+    // X = H [Re S | Im S]
+#pragma unroll
+    for (int mt = 0; mt < NB; ++mt) {
+        for (int nt = ((wave - mt * NTC) % 4 + 4) % 4; nt < NTC; nt += 4) {
+            const T* plane = nt < NB ? sSre : sSim;
+            const int c0 = 16 * (nt < NB ? nt : nt - NB);
+            acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                if (ks < ksteps) {
+                    const T bv = plane[(4 * ks + (lane >> 4)) * LS + c0 + (lane & 15)];
+                    acc = mfma16(hreg[mt][ks], bv, acc);
+                }
+            }
+            T* out = nt < NB ? sXre : sXim;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                out[(16 * mt + mfma_row<T>(lane, r)) * LS + c0 + (lane & 15)] = acc[r];
+        }
+    }
+    if (!HERM) {
+        // Y = S H (H real symmetric: the B operand H[k][j] has the A layout)
+#pragma unroll
+        for (int mt = 0; mt < 2 * NB; ++mt) {
+            const T* plane = mt < NB ? sSre : sSim;
+            const int r0 = 16 * (mt < NB ? mt : mt - NB);
+#pragma unroll
+            for (int nt = 0; nt < NB; ++nt) {
+                if (((mt * NB + nt) & 3) != wave) continue;
+                acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    if (ks < ksteps) {
+                        const T av = plane[(r0 + (lane & 15)) * LS + 4 * ks + (lane >> 4)];
+                        acc = mfma16(av, hreg[nt][ks], acc);
+                    }
+                }
+                T* out = mt < NB ? sYre : sYim;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    out[(r0 + mfma_row<T>(lane, r)) * LS + 16 * nt + (lane & 15)] = acc[r];
+            }
+        }
+    }
+    __syncthreads();
+
+    // -i[H, sigma], damping and correction lines
+    T ar[EPT], ai[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int i = ei[q], j = ej[q];
+        if (tid + q * kBlock >= NN) {
+            ar[q] = ai[q] = (T)0;
+            continue;
+        }
+        T cr, ci;
+        if (HERM) {
+            cr = sXre[i * LS + j] - sXre[j * LS + i];
+            ci = sXim[i * LS + j] + sXim[j * LS + i];
+        } else {
+            cr = sXre[i * LS + j] - sYre[i * LS + j];
+            ci = sXim[i * LS + j] - sYim[i * LS + j];
+        }
+        const T dl = (i != j) ? bt.delta[i] + bt.delta[j] : (T)0;
+        ar[q] = ci - (gam + dl) * own[q].re;
+        ai[q] = -cr - (gam + dl) * own[q].im;
+    }
+    // coupling lines: links outermost, the thread's elements innermost
+    const NbSrc<T> nbs{J.sig0[sp.in], J.rest[sp.in], N};
+    const int n_minus = bt.count[4];
+    for (int a = 0; a < n_minus; ++a) {
+        const int s = bt.msite[a], nb = bt.mnb[a];
+        const T ml = bt.mml[a], mc = bt.mmc[a];
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int i = ei[q], j = ej[q];
+            if (tid + q * kBlock < NN && (i == s || j == s)) {
+                const bool col = (j == s) && (i != s);
+                const cpx<T> x = (HERM && col) ? cconj(load_nb<T>(nbs, nb, s, i))
+                                               : load_nb<T>(nbs, nb, i, j);
+                const T vx = (T)((i == s) - (j == s)), vo = (T)((i == s) + (j == s));
+                const T thr = ml * vo, thi = mc * vx;
+                ar[q] += thr * x.re - thi * x.im;
+                ai[q] += thr * x.im + thi * x.re;
+            }
+        }
+    }
+    if (lev < D) {
+        for (int l = 0; l < W; ++l) {
+            const int s = bt.site[l], nb = bt.pnb[l];
+            const T pa = bt.pa[l];
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) {
+                const int i = ei[q], j = ej[q];
+                if (tid + q * kBlock < NN && i != j && (i == s || j == s)) {
+                    const bool col = (j == s);
+                    const cpx<T> x = (HERM && col) ? cconj(load_nb<T>(nbs, nb, s, i))
+                                                   : load_nb<T>(nbs, nb, i, j);
+                    const T a = col ? -pa : pa;  // i * pa * vx * x
+                    ar[q] -= a * x.im;
+                    ai[q] += a * x.re;
+                }
+            }
+        }
+    }
+    // RK4 stage combination
+    const T h = (T)(sp.hmul * J.dt);
+    const T w_in = (T)sp.w_in;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int e = tid + q * kBlock;
+        if (e >= NN) continue;
+        const T yr = w_in * own[q].re + acc_base[q].re + h * ar[q];
+        const T yi = w_in * own[q].im + acc_base[q].im + h * ai[q];
+        st<T>(J.rest[sp.out], base + e, cpx<T>{yr, yi});
+    }
+}
+
+template <typename T, int NB, bool HERM>
+size_t mfma_lds_bytes(int N, int W) {
+    constexpr int NP = 16 * NB;
+    constexpr int LS = NP + 1;
+    return sizeof(T) * (size_t)NP * LS * (HERM ? 4 : 6) + (size_t)W * (4 * 4 + 3 * sizeof(T)) +
+           (size_t)N * sizeof(T) + 8 * 4;
+}
+
 }  // namespace
+
+int bulk_mfma_blocks(int N, bool h_complex, int precision) {
+    if (N < 16 || h_complex || (precision == 0 && N > 48)) return 0;
+    return (N + 15) / 16;
+}
 
 int bulk_ados_per_tile(int N) {
     const int NN = N * N;
@@ -427,13 +784,52 @@ hipError_t launch_enumerate(const Tables& t, hipStream_t stream) {
     return hipGetLastError();
 }
 
+template <typename T, int NB, bool HERM>
+static hipError_t launch_mfma_t(const Job& single, const Job* jobs_dev, int n_jobs,
+                                int total_tiles, const StageSpec& sp, hipStream_t stream) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bulk_mfma<T, NB, HERM>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (a != hipSuccess) return a;
+        attr_set = true;
+    }
+    const size_t lds = mfma_lds_bytes<T, NB, HERM>(single.t.N, single.t.W);
+    hipLaunchKernelGGL((k_bulk_mfma<T, NB, HERM>), dim3(total_tiles), dim3(kBlock), lds, stream,
+                       single, jobs_dev, n_jobs, sp);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_mfma(int nb, bool herm, const Job& single, const Job* jobs_dev,
+                              int n_jobs, int total_tiles, const StageSpec& sp,
+                              hipStream_t stream) {
+#define HEOM_MFMA_CASE(NBV)                                                                   \
+    case NBV:                                                                                 \
+        return herm ? launch_mfma_t<T, NBV, true>(single, jobs_dev, n_jobs, total_tiles, sp,  \
+                                                  stream)                                     \
+                    : launch_mfma_t<T, NBV, false>(single, jobs_dev, n_jobs, total_tiles, sp, \
+                                                   stream);
+    switch (nb) {
+        HEOM_MFMA_CASE(1)
+        HEOM_MFMA_CASE(2)
+        HEOM_MFMA_CASE(3)
+        HEOM_MFMA_CASE(4)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef HEOM_MFMA_CASE
+}
+
 template <typename T>
 static hipError_t launch_stage_t(const Job& single, const Job* jobs_dev, int n_jobs,
-                                 int total_tiles, const StageSpec& sp, hipStream_t stream) {
+                                 int total_tiles, const StageSpec& sp, hipStream_t stream,
+                                 hipEvent_t ev_begin, hipEvent_t ev_end) {
     const int N = single.t.N;
     const int NN = N * N;
-    // sigma_0: FP64 LDS for H and sigma_0
-    const size_t lds0 = 4 * (size_t)NN * sizeof(double);
+    // sigma_0: FP64 LDS for H, sigma_0, per-mode weights and sites, per-state delta
+    const size_t lds0 = 4 * (size_t)NN * sizeof(double) + (size_t)single.t.W * 12 +
+                        (size_t)N * sizeof(double);
     // Allow dynamic LDS above 64 KiB (N up to 64 in FP64).
     static bool attr_set = false;
     if (!attr_set) {
@@ -450,20 +846,40 @@ static hipError_t launch_stage_t(const Job& single, const Job* jobs_dev, int n_j
                        sp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || total_tiles == 0) return e;
-    // bulk: LDS for H and the G-ADO tile.  In a batched launch the largest N
-    // of the batch sizes the allocation (`single` carries it).
-    const int G = bulk_ados_per_tile(N);
-    const size_t lds = 2 * (size_t)NN * sizeof(T) * (1 + G);
+    // MFMA path for 16 <= N (real H); FP64 above N = 48 would need more than
+    // 160 KiB of LDS and stays on the FMA path.
+    const int nb = bulk_mfma_blocks(N, single.t.h_complex != 0, sizeof(T) == 8 ? 0 : 1);
+    if (nb > 0) {
+        const bool herm = single.herm != 0;
+        if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
+        e = launch_mfma<T>(nb, herm, single, jobs_dev, n_jobs, total_tiles, sp, stream);
+        if (e != hipSuccess) return e;
+        if (ev_end) e = hipEventRecord(ev_end, stream);
+        return e;
+    }
+    // bulk: in a batched launch `single` carries the largest N of the batch.
+    // LDS for H and the G-ADO tile: 2 n^2 (1 + G(n)) is not monotone in n, so
+    // a batch whose largest matrix is N x N takes the maximum over n <= N.
+    size_t lds_elems = 0;
+    for (int n = 1; n <= N; ++n)
+        lds_elems = std::max(lds_elems, 2 * (size_t)n * n * (1 + bulk_ados_per_tile(n)));
+    const size_t lds = lds_elems * sizeof(T);
+    if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_bulk_fma<T>, dim3(total_tiles), dim3(kBlock), lds, stream, single,
                        jobs_dev, n_jobs, sp);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev_end) e = hipEventRecord(ev_end, stream);
+    return e;
 }
 
 hipError_t launch_stage(const Job& single, const Job* jobs_dev, int n_jobs, int total_tiles,
-                        int precision, const StageSpec& sp, hipStream_t stream) {
+                        int precision, const StageSpec& sp, hipStream_t stream,
+                        hipEvent_t ev_begin, hipEvent_t ev_end) {
     if (precision == 0)
-        return launch_stage_t<double>(single, jobs_dev, n_jobs, total_tiles, sp, stream);
-    return launch_stage_t<float>(single, jobs_dev, n_jobs, total_tiles, sp, stream);
+        return launch_stage_t<double>(single, jobs_dev, n_jobs, total_tiles, sp, stream,
+                                      ev_begin, ev_end);
+    return launch_stage_t<float>(single, jobs_dev, n_jobs, total_tiles, sp, stream, ev_begin,
+                                 ev_end);
 }
 
 }  // namespace heom

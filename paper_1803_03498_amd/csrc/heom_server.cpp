@@ -1,0 +1,648 @@
+// Continuous-batching server for independent HEOM propagations on one GPU.
+//
+// Requests (a problem, its initial states and step count) are admitted by
+// memory footprint into a caller-owned device arena.  Every admitted request
+// joins the active set at an RK4-step boundary; each macro-step then advances
+// every active propagation by one RK4 step with batched launches: per stage,
+// one sigma_0 launch and one bulk launch per kernel variant (precision,
+// FMA/MFMA path) whose grid covers the ADO tiles of all active jobs.  The
+// arithmetic of a job does not depend on the batch it runs in (fixed
+// tile -> ADO mapping, no cross-job reductions), so a result is the same alone
+// and in the mix.  Finished requests leave at a step boundary; their records
+// are copied to pinned host memory and their arena ranges are freed once the
+// copy has completed on the stream.
+//
+// Independent propagations (disorder realisations, dipole directions) are the
+// parallelism the paper runs side by side for rotational averages and
+// polarisation sequences (section "Distributed memory HEOM implementation").
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "heom.h"
+#include "heom_internal.h"
+
+namespace {
+
+constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr int kMaxRuns = 8;
+constexpr size_t kPinnedPool = size_t(256) << 20;
+
+// First-fit allocator of 256-byte-aligned ranges of [0, size).
+class RangeAllocator {
+public:
+    void reset(size_t size) {
+        free_.clear();
+        if (size) free_[0] = size;
+    }
+    bool alloc(size_t bytes, size_t* off) {
+        bytes = align256(std::max<size_t>(bytes, 1));
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes, start = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = align256(std::max<size_t>(bytes, 1));
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+private:
+    std::map<size_t, size_t> free_;
+};
+
+struct Req {
+    uint64_t ticket = 0;
+    std::vector<double> h_re, h_im, rho0, mu;
+    std::vector<heom_bath> baths;
+    heom_problem prob{};
+    int n_runs = 1, record_every = 1, kind = 0, ground = 0, hermitian = 0;
+    int64_t n_steps = 0, n_rec = 0;
+    int rd = 0;
+    double dt = 0.0;
+    heom_info info{};
+    size_t state_bytes = 0, work_bytes = 0, footprint = 0, pinned_bytes = 0;
+    // runtime
+    enum Phase { QUEUED, ACTIVE, DRAINING, DONE } phase = QUEUED;
+    heom_hierarchy* h = nullptr;
+    size_t arena_off = 0, pinned_off = 0;
+    bool has_arena = false, has_pinned = false;
+    std::vector<heom::Job> jobs;
+    int64_t steps_done = 0;
+    hipEvent_t done_ev = nullptr;
+    bool cancel = false;
+    heom_status status = HEOM_PENDING;
+    std::vector<double> records;
+    double t_submit = 0.0, t_admit = 0.0, t_finish = 0.0;
+};
+
+struct Group {
+    int precision = 0, nb = 0, herm = 0;
+    int job_off = 0, n_jobs = 0, tiles = 0;
+    heom::Job sizing{};
+};
+
+}  // namespace
+
+struct heom_server {
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    int max_active = 1;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    RangeAllocator arena_alloc, pinned_alloc;
+    char* pinned = nullptr;
+    heom::Job* jobs_dev = nullptr;    // in the arena
+    heom::Job* jobs_stage = nullptr;  // pinned staging for the job table
+    size_t jobs_cap = 0;
+    hipEvent_t stage_ev = nullptr;
+    hipEvent_t step_ev[2] = {nullptr, nullptr};
+    int64_t macro = 0;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Req*> pending;
+    std::map<uint64_t, std::unique_ptr<Req>> all;
+    std::vector<Req*> active, draining;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    heom_status fatal = HEOM_OK;
+    std::string fatal_msg;
+    std::vector<Group> groups;
+    bool dirty = false;
+    std::thread thr;
+
+    void run();
+    void admit();
+    bool setup(Req* r);
+    void start_drain(Req* r);
+    void finish_draining();
+    void finish(Req* r, heom_status st);  // caller holds mu
+    void release_resources(Req* r);
+    bool rebuild();
+    bool launch_macro_step();
+    void fail_all(const char* what, hipError_t e);         // takes mu
+    void fail_all_locked(const char* what, hipError_t e);  // caller holds mu
+};
+
+namespace {
+
+heom_status srv_fail(heom_status s, const std::string& msg) {
+    heom::set_last_error(msg);
+    return s;
+}
+
+}  // namespace
+
+void heom_server::finish(Req* r, heom_status st) {
+    r->status = st;
+    r->phase = Req::DONE;
+    r->t_finish = heom::monotonic_seconds();
+    cv_done.notify_all();
+}
+
+void heom_server::release_resources(Req* r) {
+    if (r->h) {
+        heom_destroy(r->h);
+        r->h = nullptr;
+    }
+    if (r->has_arena) arena_alloc.release(r->arena_off, r->footprint);
+    if (r->has_pinned) pinned_alloc.release(r->pinned_off, r->pinned_bytes);
+    r->has_arena = r->has_pinned = false;
+    if (r->done_ev) {
+        (void)hipEventDestroy(r->done_ev);
+        r->done_ev = nullptr;
+    }
+}
+
+void heom_server::fail_all(const char* what, hipError_t e) {
+    std::lock_guard<std::mutex> lk(mu);
+    fail_all_locked(what, e);
+}
+
+void heom_server::fail_all_locked(const char* what, hipError_t e) {
+    fatal = HEOM_E_DEVICE;
+    fatal_msg = std::string(what) + ": " + hipGetErrorString(e);
+    for (Req* r : active) finish(r, HEOM_E_DEVICE);
+    for (Req* r : draining) finish(r, HEOM_E_DEVICE);
+    for (Req* r : pending) finish(r, HEOM_E_DEVICE);
+    active.clear();
+    draining.clear();
+    pending.clear();
+    stop = true;
+}
+
+// Device and pinned layout of one request (offsets from its ranges):
+//   arena: tables | per run: sigma0, rest, workspace
+//   pinned: per run: rho0, control block, records, status
+bool heom_server::setup(Req* r) {
+    char* base = arena + r->arena_off;
+    char* pin = pinned + r->pinned_off;
+    hipError_t e;
+    heom_status s = heom_build_hierarchy(&r->prob, base, r->info.tables_bytes, stream, &r->h);
+    if (s != HEOM_OK) {
+        std::lock_guard<std::mutex> lk(mu);
+        finish(r, s);
+        return false;
+    }
+    const int N = r->info.n_states;
+    const size_t NN = (size_t)N * N;
+    size_t off = align256(r->info.tables_bytes);
+    size_t poff = 0;
+    r->jobs.clear();
+    for (int k = 0; k < r->n_runs; ++k) {
+        heom_state st;
+        st.sigma0 = base + off;
+        off += align256(r->info.sigma0_bytes);
+        st.rest = base + off;
+        off += align256(std::max<size_t>(r->info.rest_bytes, 1));
+        char* work = base + off;
+        off += r->work_bytes;
+        heom::Job j = heom::bind_workspace(r->h, st, work, r->dt, r->n_steps, r->record_every,
+                                           r->kind, r->ground, r->hermitian);
+        // initial state: rho0 for sigma_0, zero elsewhere
+        char* prho = pin + poff;
+        poff += align256(NN * 16);
+        std::memcpy(prho, r->rho0.data() + 2 * NN * k, NN * 16);
+        char* pctl = pin + poff;
+        poff += align256(heom::control_bytes(N));
+        std::memset(pctl, 0, heom::control_bytes(N));
+        if (r->kind == HEOM_OBS_DIPOLE) std::memcpy(pctl + 1024, r->mu.data() + (size_t)N * k, N * 8);
+        poff += align256((size_t)r->n_rec * r->rd * 8) + 256;  // records + status (drain)
+        if ((e = hipMemcpyAsync(st.sigma0, prho, NN * 16, hipMemcpyHostToDevice, stream)) ||
+            (r->info.rest_bytes &&
+             (e = hipMemsetAsync(st.rest, 0, r->info.rest_bytes, stream))) ||
+            (e = hipMemcpyAsync(work, pctl, heom::control_bytes(N), hipMemcpyHostToDevice, stream))) {
+            fail_all("request setup", e);
+            return false;
+        }
+        r->jobs.push_back(j);
+    }
+    return true;
+}
+
+void heom_server::admit() {
+    std::unique_lock<std::mutex> lk(mu);
+    while (!pending.empty() && (int)(active.size() + draining.size()) < max_active) {
+        Req* r = pending.front();
+        if (r->cancel) {
+            pending.pop_front();
+            finish(r, HEOM_E_CANCELLED);
+            continue;
+        }
+        size_t aoff = 0, poff = 0;
+        if (!arena_alloc.alloc(r->footprint, &aoff)) break;
+        if (!pinned_alloc.alloc(r->pinned_bytes, &poff)) {
+            arena_alloc.release(aoff, r->footprint);
+            break;
+        }
+        pending.pop_front();
+        r->arena_off = aoff;
+        r->pinned_off = poff;
+        r->has_arena = r->has_pinned = true;
+        lk.unlock();
+        const bool ok = setup(r);
+        lk.lock();
+        if (!ok) {
+            release_resources(r);
+            if (r->phase != Req::DONE) finish(r, fatal != HEOM_OK ? fatal : HEOM_E_DEVICE);
+            if (stop) return;
+            continue;
+        }
+        r->phase = Req::ACTIVE;
+        r->t_admit = heom::monotonic_seconds();
+        r->steps_done = 0;
+        active.push_back(r);
+        dirty = true;
+    }
+}
+
+bool heom_server::rebuild() {
+    groups.clear();
+    std::map<std::tuple<int, int, int>, std::vector<const heom::Job*>> by_key;
+    for (Req* r : active) {
+        const int prec = heom::hierarchy_precision(r->h);
+        for (const heom::Job& j : r->jobs) {
+            const int nb = heom::bulk_mfma_blocks(j.t.N, j.t.h_complex != 0, prec);
+            by_key[std::make_tuple(prec, nb, nb ? j.herm : 0)].push_back(&j);
+        }
+    }
+    size_t n = 0;
+    for (auto& kv : by_key) n += kv.second.size();
+    if (n > jobs_cap) {
+        fail_all("job table overflow", hipErrorInvalidValue);
+        return false;
+    }
+    if (stage_ev) (void)hipEventSynchronize(stage_ev);  // staging buffer free again
+    int off = 0;
+    for (auto& kv : by_key) {
+        Group g;
+        g.precision = std::get<0>(kv.first);
+        g.nb = std::get<1>(kv.first);
+        g.herm = std::get<2>(kv.first);
+        g.job_off = off;
+        g.n_jobs = (int)kv.second.size();
+        g.sizing = *kv.second.front();
+        int maxN = 0, maxW = 0, tiles = 0;
+        for (const heom::Job* j : kv.second) {
+            heom::Job c = *j;
+            c.tile_begin = tiles;
+            tiles += (c.t.n_ado > 1) ? c.n_tiles : 0;
+            maxN = std::max(maxN, c.t.N);
+            maxW = std::max(maxW, c.t.W);
+            jobs_stage[off++] = c;
+        }
+        g.tiles = tiles;
+        g.sizing.t.N = maxN;
+        g.sizing.t.W = maxW;
+        g.sizing.herm = g.herm;
+        if (g.nb == 0) g.sizing.t.h_complex = 1;  // selects the FMA path for any N
+        groups.push_back(g);
+    }
+    hipError_t e = hipMemcpyAsync(jobs_dev, jobs_stage, n * sizeof(heom::Job),
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(stage_ev, stream);
+    if (e != hipSuccess) {
+        fail_all("job table upload", e);
+        return false;
+    }
+    dirty = false;
+    return true;
+}
+
+bool heom_server::launch_macro_step() {
+    heom::StageSpec sp[4];
+    heom::rk4_stage_specs(sp);
+    hipError_t e = hipSuccess;
+    if (macro >= 2) e = hipEventSynchronize(step_ev[macro % 2]);  // at most two steps in flight
+    for (int k = 0; k < 4 && e == hipSuccess; ++k)
+        for (const Group& g : groups) {
+            e = heom::launch_stage(g.sizing, jobs_dev + g.job_off, g.n_jobs, g.tiles, g.precision,
+                                   sp[k], stream);
+            if (e != hipSuccess) break;
+        }
+    if (e == hipSuccess) e = hipEventRecord(step_ev[macro % 2], stream);
+    if (e != hipSuccess) {
+        fail_all("macro-step launch", e);
+        return false;
+    }
+    ++macro;
+    return true;
+}
+
+void heom_server::start_drain(Req* r) {
+    char* pin = pinned + r->pinned_off;
+    const int N = r->info.n_states;
+    const size_t NN = (size_t)N * N;
+    size_t poff = 0;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < r->n_runs && e == hipSuccess; ++k) {
+        poff += align256(NN * 16) + align256(heom::control_bytes(N));
+        const heom::Job& j = r->jobs[k];
+        const size_t rec_bytes = (size_t)r->n_rec * r->rd * 8;
+        e = hipMemcpyAsync(pin + poff, j.records, rec_bytes, hipMemcpyDeviceToHost, stream);
+        poff += align256(rec_bytes);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(pin + poff, j.status, 4, hipMemcpyDeviceToHost, stream);
+        poff += 256;
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(r->done_ev, stream);
+    if (e != hipSuccess) {
+        finish(r, HEOM_E_DEVICE);
+        fail_all_locked("result copy", e);
+        return;
+    }
+    r->phase = Req::DRAINING;
+    draining.push_back(r);
+}
+
+void heom_server::finish_draining() {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto it = draining.begin(); it != draining.end();) {
+        Req* r = *it;
+        if (hipEventQuery(r->done_ev) != hipSuccess) {
+            ++it;
+            continue;
+        }
+        const char* pin = pinned + r->pinned_off;
+        const int N = r->info.n_states;
+        const size_t NN = (size_t)N * N;
+        const size_t rec_doubles = (size_t)r->n_rec * r->rd;
+        r->records.assign(rec_doubles * r->n_runs, 0.0);
+        size_t poff = 0;
+        int32_t bad = 0;
+        for (int k = 0; k < r->n_runs; ++k) {
+            poff += align256(NN * 16) + align256(heom::control_bytes(N));
+            std::memcpy(r->records.data() + rec_doubles * k, pin + poff, rec_doubles * 8);
+            poff += align256(rec_doubles * 8);
+            int32_t st;
+            std::memcpy(&st, pin + poff, 4);
+            bad |= st;
+            poff += 256;
+        }
+        release_resources(r);
+        finish(r, r->cancel ? HEOM_E_CANCELLED : (bad ? HEOM_E_NUMERIC : HEOM_OK));
+        it = draining.erase(it);
+    }
+}
+
+void heom_server::run() {
+    (void)hipSetDevice(device);
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            if (stop) break;
+            if (active.empty() && draining.empty())
+                cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+            if (stop) break;
+        }
+        finish_draining();
+        admit();
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (stop) break;
+            // cancelled active requests leave at this step boundary
+            for (auto it = active.begin(); it != active.end();) {
+                if ((*it)->cancel) {
+                    start_drain(*it);
+                    it = active.erase(it);
+                    dirty = true;
+                } else {
+                    ++it;
+                }
+            }
+        }
+        if (active.empty()) {
+            if (!draining.empty()) std::this_thread::yield();
+            continue;
+        }
+        if (dirty && !rebuild()) break;
+        if (!launch_macro_step()) break;
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto it = active.begin(); it != active.end();) {
+            Req* r = *it;
+            if (++r->steps_done >= r->n_steps) {
+                start_drain(r);
+                it = active.erase(it);
+                dirty = true;
+            } else {
+                ++it;
+            }
+        }
+    }
+    // wait for the device before the arena is handed back
+    (void)hipStreamSynchronize(stream);
+}
+
+extern "C" {
+
+heom_status heom_server_create(void* arena_dev, size_t arena_bytes, int32_t max_active,
+                               void* stream, heom_server** out) {
+    if (!out) return srv_fail(HEOM_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!arena_dev || reinterpret_cast<uintptr_t>(arena_dev) % 256)
+        return srv_fail(HEOM_E_INVAL, "arena must be non-NULL and 256-byte aligned");
+    if (max_active < 1 || max_active > 4096) return srv_fail(HEOM_E_INVAL, "max_active outside 1..4096");
+    auto* s = new heom_server();
+    s->arena = static_cast<char*>(arena_dev);
+    s->max_active = max_active;
+    s->stream = static_cast<hipStream_t>(stream);
+    s->jobs_cap = (size_t)max_active * kMaxRuns;
+    const size_t table_bytes = align256(s->jobs_cap * sizeof(heom::Job));
+    if (arena_bytes <= table_bytes) {
+        delete s;
+        return srv_fail(HEOM_E_NOMEM, "arena smaller than the job table");
+    }
+    s->jobs_dev = reinterpret_cast<heom::Job*>(s->arena);
+    s->arena_bytes = arena_bytes;
+    // the job table occupies the start of the arena
+    s->arena_alloc.reset(arena_bytes);
+    size_t off;
+    s->arena_alloc.alloc(table_bytes, &off);
+    hipError_t e = hipGetDevice(&s->device);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->pinned), kPinnedPool, 0);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&s->jobs_stage), table_bytes, 0);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->stage_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->step_ev[0], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->step_ev[1], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        if (s->pinned) (void)hipHostFree(s->pinned);
+        if (s->jobs_stage) (void)hipHostFree(s->jobs_stage);
+        delete s;
+        return srv_fail(HEOM_E_DEVICE, std::string("server setup: ") + hipGetErrorString(e));
+    }
+    s->pinned_alloc.reset(kPinnedPool);
+    s->thr = std::thread([s] { s->run(); });
+    *out = s;
+    return HEOM_OK;
+}
+
+heom_status heom_submit(heom_server* s, const heom_request* q, uint64_t* ticket) {
+    if (!s || !q || !ticket) return srv_fail(HEOM_E_INVAL, "NULL argument");
+    heom_info info;
+    heom_status st = heom_plan(&q->problem, &info);
+    if (st != HEOM_OK) return srv_fail(st, heom_last_error());
+    if (q->n_runs < 1 || q->n_runs > kMaxRuns) return srv_fail(HEOM_E_INVAL, "n_runs outside 1..8");
+    if (q->n_steps < 1 || q->record_every < 1) return srv_fail(HEOM_E_INVAL, "n_steps or record_every < 1");
+    if (!(q->dt_fs > 0.0) || !std::isfinite(q->dt_fs)) return srv_fail(HEOM_E_INVAL, "dt must be > 0");
+    if (!q->rho0) return srv_fail(HEOM_E_INVAL, "rho0 is NULL");
+    const int kind = q->obs.kind;
+    if (kind != HEOM_OBS_POPULATION && kind != HEOM_OBS_DIPOLE)
+        return srv_fail(HEOM_E_INVAL, "observable kind unknown");
+    const int N = info.n_states;
+    if (kind == HEOM_OBS_DIPOLE && (!q->obs.mu || q->obs.ground < 0 || q->obs.ground >= N))
+        return srv_fail(HEOM_E_INVAL, "dipole observable needs mu and a ground index in range");
+    double rate = 0.0;
+    heom::problem_rate_bound(&q->problem, &rate);
+    if (q->dt_fs * rate > heom::rk4_real_limit())
+        return srv_fail(HEOM_E_UNSTABLE, "dt times the rate bound exceeds the RK4 interval");
+
+    auto r = std::make_unique<Req>();
+    const size_t NN = (size_t)N * N;
+    r->h_re.assign(q->problem.h_re_cm, q->problem.h_re_cm + NN);
+    if (q->problem.h_im_cm) r->h_im.assign(q->problem.h_im_cm, q->problem.h_im_cm + NN);
+    r->baths.assign(q->problem.baths, q->problem.baths + q->problem.n_baths);
+    r->prob = q->problem;
+    r->prob.h_re_cm = r->h_re.data();
+    r->prob.h_im_cm = q->problem.h_im_cm ? r->h_im.data() : nullptr;
+    r->prob.baths = r->baths.data();
+    r->n_runs = q->n_runs;
+    r->record_every = q->record_every;
+    r->kind = kind;
+    r->ground = kind == HEOM_OBS_DIPOLE ? q->obs.ground : 0;
+    r->hermitian = q->hermitian ? 1 : 0;
+    r->n_steps = q->n_steps;
+    r->dt = q->dt_fs;
+    r->rho0.assign(q->rho0, q->rho0 + 2 * NN * q->n_runs);
+    if (kind == HEOM_OBS_DIPOLE) r->mu.assign(q->obs.mu, q->obs.mu + (size_t)N * q->n_runs);
+    r->info = info;
+    r->n_rec = heom_record_count(q->n_steps, q->record_every);
+    r->rd = heom_record_doubles(N, kind);
+    r->work_bytes = align256(heom_propagate_work_bytes(&info, q->n_steps, q->record_every, kind));
+    r->state_bytes = align256(info.sigma0_bytes) + align256(std::max<size_t>(info.rest_bytes, 1));
+    r->footprint = align256(info.tables_bytes) + (size_t)q->n_runs * (r->state_bytes + r->work_bytes);
+    r->pinned_bytes = (size_t)q->n_runs * (align256(NN * 16) + align256(heom::control_bytes(N)) +
+                                           align256((size_t)r->n_rec * r->rd * 8) + 256);
+    const size_t usable = s->arena_bytes - align256(s->jobs_cap * sizeof(heom::Job));
+    if (r->footprint > usable || r->pinned_bytes > kPinnedPool)
+        return srv_fail(HEOM_E_NOMEM, "request can never fit the arena");
+    r->t_submit = heom::monotonic_seconds();
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return srv_fail(s->fatal != HEOM_OK ? s->fatal : HEOM_E_INVAL,
+                                 s->fatal_msg.empty() ? "server stopped" : s->fatal_msg);
+    r->ticket = s->next_ticket++;
+    *ticket = r->ticket;
+    s->pending.push_back(r.get());
+    s->all[r->ticket] = std::move(r);
+    s->cv_work.notify_all();
+    return HEOM_OK;
+}
+
+static void fill_result(const Req* r, heom_result* out) {
+    out->status = r->status;
+    out->n_records = r->n_rec;
+    out->record_doubles = r->rd;
+    out->records = r->phase == Req::DONE && !r->records.empty() ? r->records.data() : nullptr;
+    out->t_submit_s = r->t_submit;
+    out->t_admit_s = r->t_admit;
+    out->t_finish_s = r->t_finish;
+}
+
+heom_status heom_poll(heom_server* s, uint64_t ticket, heom_result* out) {
+    if (!s) return srv_fail(HEOM_E_INVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return srv_fail(HEOM_E_NOTFOUND, "unknown ticket");
+    const Req* r = it->second.get();
+    if (out) fill_result(r, out);
+    return r->phase == Req::DONE ? r->status : HEOM_PENDING;
+}
+
+heom_status heom_wait(heom_server* s, uint64_t ticket, double timeout_s, heom_result* out) {
+    if (!s) return srv_fail(HEOM_E_INVAL, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return srv_fail(HEOM_E_NOTFOUND, "unknown ticket");
+    Req* r = it->second.get();
+    auto done = [&] { return r->phase == Req::DONE; };
+    if (timeout_s < 0)
+        s->cv_done.wait(lk, done);
+    else
+        s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done);
+    if (out) fill_result(r, out);
+    return r->phase == Req::DONE ? r->status : HEOM_PENDING;
+}
+
+heom_status heom_cancel(heom_server* s, uint64_t ticket) {
+    if (!s) return srv_fail(HEOM_E_INVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return srv_fail(HEOM_E_NOTFOUND, "unknown ticket");
+    it->second->cancel = true;
+    s->cv_work.notify_all();
+    return HEOM_OK;
+}
+
+heom_status heom_release(heom_server* s, uint64_t ticket) {
+    if (!s) return srv_fail(HEOM_E_INVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return srv_fail(HEOM_E_NOTFOUND, "unknown ticket");
+    if (it->second->phase != Req::DONE) return srv_fail(HEOM_E_INVAL, "request not finished");
+    s->all.erase(it);
+    return HEOM_OK;
+}
+
+heom_status heom_server_destroy(heom_server* s) {
+    if (!s) return HEOM_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv_work.notify_all();
+    }
+    if (s->thr.joinable()) s->thr.join();
+    (void)hipStreamSynchronize(s->stream);
+    for (auto& kv : s->all) {
+        Req* r = kv.second.get();
+        s->release_resources(r);
+    }
+    if (s->pinned) (void)hipHostFree(s->pinned);
+    if (s->jobs_stage) (void)hipHostFree(s->jobs_stage);
+    if (s->stage_ev) (void)hipEventDestroy(s->stage_ev);
+    for (auto& e : s->step_ev)
+        if (e) (void)hipEventDestroy(e);
+    delete s;
+    return HEOM_OK;
+}
+
+}  // extern "C"
