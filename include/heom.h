@@ -206,6 +206,16 @@ heom_status heom_get_state(const heom_hierarchy* h, heom_state s, void* host_sig
 heom_status heom_set_state(const heom_hierarchy* h, heom_state s, const void* host_sigma0,
                            const void* host_rest, void* stream);
 
+/* Host only: linear absorption spectrum from dipole-correlation records
+ * (eq. lin_abs_mukamel on a finite window, section "Linear absorption
+ * spectra"):  S(w_k) = Re sum_p sum_n c_n exp(i w_k t_n) P_p(t_n) dt,
+ * trapezoid weights c_0 = c_last = 1/2, t_n = n * dt_fs.  P is interleaved
+ * complex [n_dir][n_t] (the Re P, Im P columns of the records); omega_cm
+ * [n_omega] in cm^-1 (relative to the rotating frame, if one was used);
+ * S [n_omega] is written.  FP64. */
+heom_status heom_spectrum(const double* P, int32_t n_dir, int64_t n_t, double dt_fs,
+                          const double* omega_cm, int64_t n_omega, double* S);
+
 /* Release a handle (does not touch caller memory). */
 heom_status heom_destroy(heom_hierarchy* h);
 

@@ -18,7 +18,7 @@ from . import _abi
 from ._abi import FP32_MIXED, FP64, OBS_DIPOLE, OBS_POPULATION, HeomError, check, load
 
 __all__ = ["FP64", "FP32_MIXED", "OBS_POPULATION", "OBS_DIPOLE", "HeomError", "Problem", "plan",
-           "Hierarchy", "Server", "load"]
+           "Hierarchy", "Server", "spectrum", "load"]
 
 
 def _torch():
@@ -61,6 +61,16 @@ def plan(prob, precision=FP64):
     info = _abi.HeomInfo()
     check(load().heom_plan(ctypes.byref(p.struct), ctypes.byref(info)))
     return {f: getattr(info, f) for f, _ in _abi.HeomInfo._fields_}
+
+
+def spectrum(P, dt_fs, omega_cm):
+    """heom_spectrum: linear absorption from P [n_dir, n_t] (complex)."""
+    P = np.ascontiguousarray(np.atleast_2d(P), dtype=np.complex128)
+    w = np.ascontiguousarray(omega_cm, dtype=np.float64)
+    S = np.zeros(len(w))
+    check(load().heom_spectrum(P.ctypes.data, P.shape[0], P.shape[1], float(dt_fs), w.ctypes.data,
+                               len(w), S.ctypes.data))
+    return S
 
 
 def _info_struct(d):

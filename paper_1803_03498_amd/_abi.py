@@ -86,6 +86,7 @@ SIGNATURES = {
     "heom_get_state": (i32, [vp, HeomState, vp, vp, vp]),
     "heom_set_state": (i32, [vp, HeomState, vp, vp, vp]),
     "heom_destroy": (i32, [vp]),
+    "heom_spectrum": (i32, [vp, i32, i64, f64, vp, i64, vp]),
     "heom_timing_enable": (i32, [i32]),
     "heom_timing_read": (i32, [P(f64), P(i64), P(f64), i32]),
     "heom_server_create": (i32, [vp, sz, i32, vp, P(vp)]),

@@ -731,6 +731,32 @@ heom_status heom_set_state(const heom_hierarchy* h, heom_state s, const void* ho
     return HEOM_OK;
 }
 
+heom_status heom_spectrum(const double* P, int32_t n_dir, int64_t n_t, double dt_fs,
+                          const double* omega_cm, int64_t n_omega, double* S) {
+    if (!P || !omega_cm || !S || n_dir < 1 || n_t < 2 || n_omega < 0 || !(dt_fs > 0.0))
+        return fail(HEOM_E_INVAL, "spectrum: bad arguments");
+    // Sum the directions first (the transform is linear), then one trapezoid
+    // sum per frequency with the phase advanced by a rotation per sample.
+    std::vector<double> pr(n_t, 0.0), pi(n_t, 0.0);
+    for (int p = 0; p < n_dir; ++p)
+        for (int64_t n = 0; n < n_t; ++n) {
+            pr[n] += P[2 * (p * n_t + n)];
+            pi[n] += P[2 * (p * n_t + n) + 1];
+        }
+    for (int64_t k = 0; k < n_omega; ++k) {
+        const double w = omega_cm[k] * kCmToRadFs;
+        double acc = 0.0;
+        for (int64_t n = 0; n < n_t; ++n) {
+            const double ph = w * dt_fs * (double)n;  // exact phase per sample, no recurrence drift
+            const double c = std::cos(ph), sn = std::sin(ph);
+            const double wt = (n == 0 || n == n_t - 1) ? 0.5 : 1.0;
+            acc += wt * (c * pr[n] - sn * pi[n]);  // Re(e^{i ph} P)
+        }
+        S[k] = acc * dt_fs;
+    }
+    return HEOM_OK;
+}
+
 heom_status heom_destroy(heom_hierarchy* h) {
     delete h;
     return HEOM_OK;

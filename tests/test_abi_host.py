@@ -116,3 +116,22 @@ def test_edge_sizes(heom):
     p = {"H": np.array([[1.0]]), "baths": [], "temperature_K": 300.0, "depth": 3, "flags": 0}
     assert heom.plan(p)["n_ado"] == 1
     assert heom.plan(_bad(hi.dimer(), depth=0))["n_ado"] == 1
+
+
+def test_spectrum_closed_form_and_oracle(heom, orc):
+    # P(t) = exp(-i e t): trapezoid sum is a geometric series; and the library
+    # agrees with the oracle's spectrum on random dipole correlations.
+    two_pi_c = 2.0 * np.pi * 2.99792458e-5
+    dt, n_t, e_cm = 1.0, 801, -23.0
+    t = np.arange(n_t) * dt
+    P = np.exp(-1j * e_cm * two_pi_c * t)
+    w = np.linspace(-400.0, 400.0, 81)
+    S = heom.spectrum(P[None, :], dt, w)
+    r = np.exp(1j * (w - e_cm) * two_pi_c * dt)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        geo = np.where(np.abs(r - 1) > 1e-15, (1 - r**n_t) / (1 - r), n_t)
+    ref = ((geo - 0.5 * (1 + r ** (n_t - 1))) * dt).real
+    assert np.max(np.abs(S - ref)) < 1e-9 * np.max(np.abs(ref))
+    rng = np.random.default_rng(5)
+    Pr = rng.normal(size=(3, 300)) + 1j * rng.normal(size=(3, 300))
+    assert np.allclose(heom.spectrum(Pr, 2.0, w), orc.spectrum(Pr, 2.0, w), rtol=1e-12, atol=1e-12)

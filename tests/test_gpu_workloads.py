@@ -1,0 +1,149 @@
+"""Parity on the named workloads at their real sizes.
+
+* FMO-like (3060 ADOs): full 2000-step FP64 and FP32-mixed runs against the
+  oracle's stored records (tests/golden, written by make_oracle_golden.py).
+* FMO-like linear absorption (3 directions, 1 ps): dipole correlation and the
+  spectrum within 1e-4 relative.
+* 24-site (20475 ADOs) and 48-site (156849 ADOs) aggregates: the right-hand
+  side in the launch configuration the benchmark times, compared with the
+  oracle on sampled ADOs from every level (the oracle evaluates them one by
+  one; every other ADO is zero except the neighbours of the sampled ones).
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import heom_inputs as hi
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def heom():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1803_03498_amd as heom
+    heom.load()
+    return heom
+
+
+def _case(*args):
+    print("CASE", *args, flush=True)
+
+
+def _golden(name):
+    return np.loadtxt(os.path.join(HERE, "golden", name))
+
+
+# ------------------------------------------------------------- FMO-like ----
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
+def test_fmo_like_full_run(heom, precision, tol):
+    _case("fmo_like 2000 steps", precision)
+    prob = hi.fmo_like()
+    ref = _golden("fmo_like_fp64_records.txt")
+    h = heom.Hierarchy(prob, precision)
+    st = h.new_state(prob["rho0"])
+    rec = h.propagate(st, prob["dt_fs"], prob["n_steps"], 1, prob["observable"], hermitian=True)
+    got = rec[ref[:, 0].astype(int)]
+    assert np.max(np.abs(got[:, :7] - ref[:, 1:8])) <= tol
+    assert np.max(np.abs(got[:, 7] - 1.0)) <= 1e-12   # FP64 trace
+    assert np.max(got[:, 9]) <= 1e-12                  # Hermitian sigma_0
+
+
+def test_fmo_like_absorption_spectrum(heom, orc):
+    _case("fmo_like absorption")
+    runs = hi.fmo_like_absorption()
+    ref = _golden("fmo_like_absorption_P.txt")
+    P_ref = np.stack([ref[:, 1 + 2 * p] + 1j * ref[:, 2 + 2 * p] for p in range(3)])
+    w = np.arange(-1000.0, 1001.0, 1.0)
+    S_ref = orc.spectrum(P_ref, 1.0, w)
+    for precision, p_tol in ((0, 1e-12), (1, 1e-5)):
+        P = []
+        for r in runs:
+            h = heom.Hierarchy(r, precision)
+            st = h.new_state(r["rho0"])
+            rec = h.propagate(st, r["dt_fs"], r["n_steps"], 1, r["observable"], hermitian=False)
+            P.append(rec[:, 0] + 1j * rec[:, 1])
+            assert np.max(np.abs(rec[:, 2:4])) <= 1e-12  # trace stays 0
+        P = np.stack(P)
+        assert np.max(np.abs(P - P_ref)) <= p_tol
+        S = heom.spectrum(P, 1.0, w)
+        rel = np.max(np.abs(S - S_ref)) / np.max(np.abs(S_ref))
+        assert rel <= (1e-12 if precision == 0 else 1e-4), rel
+
+
+# ----------------------------------------------- aggregates, full size ----
+
+def _level_ranges(W, D, width):
+    """A block of `width` ADOs at the start of every level >= 1 and at the end."""
+    from math import comb
+    starts = [comb(W + L - 1, W) for L in range(1, D + 1)]
+    n = comb(W + D, W)
+    out = [(s, min(s + width, n)) for s in starts]
+    out.append((n - width, n))
+    return out
+
+
+def _sampled_rhs(heom, orc, prob, precision, width, seed):
+    import torch
+    N = prob["H"].shape[0]
+    W, n = orc.sizes(prob)
+    _, plus, minus, _ = orc.tables(W, prob["depth"])
+    ranges = _level_ranges(W, prob["depth"], width)
+    sample = np.unique(np.concatenate([np.arange(a, b) for a, b in ranges]))
+    nb = np.concatenate([plus[sample].ravel(), minus[sample].ravel()])
+    need = np.unique(np.concatenate([sample, nb[nb >= 0], [0]]))
+    rng = np.random.default_rng(seed)
+    vals = rng.normal(size=(len(need), N, N)) + 1j * rng.normal(size=(len(need), N, N))
+    vals = (vals + np.conj(np.transpose(vals, (0, 2, 1)))) / 2  # Hermitian ADOs
+    vals[need > 0] = vals[need > 0].astype(np.complex128 if precision == 0 else np.complex64)
+    # oracle input: zero except the needed ADOs (pages of the rest stay untouched)
+    x = np.zeros((n, N, N), np.complex128)
+    x[need] = vals
+    h = heom.Hierarchy(prob, precision)
+    s0, rest = h.new_state(vals[0])
+    idx = torch.as_tensor(need[need > 0] - 1, device="cuda")
+    rest.index_copy_(0, idx, torch.as_tensor(vals[need > 0]).to(rest.dtype).cuda())
+    out = h.new_state()
+    h.rhs((s0, rest), out, hermitian=True)
+    torch.cuda.synchronize()
+    del rest
+    got_rest = out[1][torch.as_tensor(sample - 1, device="cuda")].cpu().numpy()
+    ref = np.zeros((len(sample), N, N), np.complex128)
+    pos = {u: k for k, u in enumerate(sample)}
+    for a, b in ranges:
+        f = orc.rhs(prob, x, a, b)
+        for u in range(a, b):
+            ref[pos[u]] = f[u]
+        del f
+    return got_rest, ref
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 1e-5), (0, 1e-12)])
+def test_aggregate24_rhs_sampled(heom, orc, precision, tol):
+    _case("aggregate24 sampled rhs", precision)
+    got, ref = _sampled_rhs(heom, orc, hi.aggregate24(), precision, 40, 24)
+    assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 1e-5), (0, 1e-12)])
+def test_aggregate48_rhs_sampled(heom, orc, precision, tol):
+    _case("aggregate48 sampled rhs", precision)
+    got, ref = _sampled_rhs(heom, orc, hi.aggregate48(), precision, 12, 48)
+    assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
+
+
+def test_aggregate24_fp32_tracks_fp64(heom):
+    _case("aggregate24 fp32 vs fp64 100 steps")
+    prob = hi.aggregate24(n_steps=100)
+    recs = []
+    for precision in (0, 1):
+        h = heom.Hierarchy(prob, precision)
+        st = h.new_state(prob["rho0"])
+        recs.append(h.propagate(st, 1.0, 100, 10, hermitian=True))
+        del st, h
+    assert np.max(np.abs(recs[0][:, :24] - recs[1][:, :24])) <= 1e-5
