@@ -268,21 +268,59 @@ __device__ void record_sigma0(const Job& J, const double* sS, int64_t slot) {
     if (!finite) *J.status = 1;
 }
 
-template <typename T>
+// LDS plan of the sigma_0 kernel: H and sigma_0 in FP64, per-mode weights,
+// per-state tables, and (when they fit) the row s_l (and, for non-Hermitian
+// states, the column s_l) of every level-1 ADO e_l.
+struct Sigma0Lds {
+    size_t h, s, pa, delta, site, begin, modes, rows, cols, total;
+    bool rows_in_lds;
+};
+
+// cap: the LDS bytes the launch provides (rows are staged only if they fit).
+__host__ __device__ inline Sigma0Lds sigma0_lds(int N, int W, int tsize, bool herm, size_t cap) {
+    Sigma0Lds L{};
+    size_t o = 0;
+    const size_t NN = (size_t)N * N;
+    L.h = o; o += 16 * NN;
+    L.s = o; o += 16 * NN;
+    L.pa = o; o += 8 * (size_t)W;
+    L.delta = o; o += 8 * (size_t)N;
+    L.site = o; o += 4 * (size_t)W;
+    L.begin = o; o += 4 * (size_t)(N + 1);
+    L.modes = o; o += 4 * (size_t)W;
+    o = (o + 15) & ~size_t(15);
+    const size_t rows = 2 * (size_t)tsize * W * N;
+    L.rows_in_lds = o + rows * (herm ? 1 : 2) <= cap;
+    L.rows = o;
+    if (L.rows_in_lds) o += rows;
+    L.cols = o;
+    if (L.rows_in_lds && !herm) o += rows;
+    L.total = o;
+    return L;
+}
+
+template <typename T, int NB>
 __global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int n_jobs,
-                                                StageSpec sp) {
-    constexpr int EPT = kMaxStates * kMaxStates / kBlock;  // 16 elements per thread at N = 64
+                                                StageSpec sp, unsigned lds_cap) {
+    constexpr int EPT = (16 * NB * 16 * NB + kBlock - 1) / kBlock;
     const Job& J = (jobs == nullptr) ? single : jobs[blockIdx.x];
     const Tables& t = J.t;
     const int N = t.N, NN = N * N, W = t.W, D = t.D;
-    extern __shared__ double smem0[];
-    double* sH = smem0;                 // 2*NN
-    double* sS = smem0 + 2 * NN;        // 2*NN
-    double* sPa = sS + 2 * NN;          // W: "+" weight of mode l at n_l = 0
-    double* sDelta = sPa + W;           // N
-    int* sSite = reinterpret_cast<int*>(sDelta + N);  // W
+    const bool herm = J.herm != 0;
+    const Sigma0Lds L = sigma0_lds(N, W, (int)sizeof(T), herm, lds_cap);
+    extern __shared__ char smem_s0[];
+    double* sH = reinterpret_cast<double*>(smem_s0 + L.h);
+    double* sS = reinterpret_cast<double*>(smem_s0 + L.s);
+    double* sPa = reinterpret_cast<double*>(smem_s0 + L.pa);
+    double* sDelta = reinterpret_cast<double*>(smem_s0 + L.delta);
+    int* sSite = reinterpret_cast<int*>(smem_s0 + L.site);
+    int* sBegin = reinterpret_cast<int*>(smem_s0 + L.begin);
+    int* sModes = reinterpret_cast<int*>(smem_s0 + L.modes);
+    T* sRows = reinterpret_cast<T*>(smem_s0 + L.rows);  // [W][N] complex
+    T* sCols = reinterpret_cast<T*>(smem_s0 + L.cols);  // [W][N] complex
     const int tid = threadIdx.x;
     const bool hc = t.h_complex != 0;
+    const NbSrc<T> nbs{J.sig0[sp.in], J.rest[sp.in], N};
     for (int e = tid; e < NN; e += blockDim.x) {
         sH[2 * e] = t.h_re[e];
         sH[2 * e + 1] = hc ? t.h_im[e] : 0.0;
@@ -293,28 +331,47 @@ __global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int
     for (int l = tid; l < W; l += blockDim.x) {
         sPa[l] = (D > 0) ? t.plus_coef[l * (D + 1)] : 0.0;
         sSite[l] = t.mode_site[l];
+        sModes[l] = t.state_modes[l];
     }
-    for (int s = tid; s < N; s += blockDim.x) sDelta[s] = t.delta_state[s];
+    for (int x = tid; x <= N; x += blockDim.x) {
+        sBegin[x] = t.state_mode_begin[x];
+        if (x < N) sDelta[x] = t.delta_state[x];
+    }
+    if (D > 0 && L.rows_in_lds) {
+        for (int idx = tid; idx < W * N; idx += blockDim.x) {
+            const int l = idx / N, c = idx - (idx / N) * N;
+            const int site = t.mode_site[l];
+            const cpx<T> r = load_nb<T>(nbs, 1 + l, site, c);
+            sRows[2 * idx] = r.re;
+            sRows[2 * idx + 1] = r.im;
+            if (!herm) {
+                const cpx<T> v = load_nb<T>(nbs, 1 + l, c, site);
+                sCols[2 * idx] = v.re;
+                sCols[2 * idx + 1] = v.im;
+            }
+        }
+    }
     __syncthreads();
     if (sp.record_initial && tid == 0 && *J.step == 0) record_sigma0(J, sS, 0);
 
-    // -i [H, sigma_0] and the correction line (the damping vanishes at u = 0)
-    double ar[EPT], ai[EPT];
+    double nr[EPT], ni[EPT];
+    const double h = sp.hmul * J.dt;
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
         const int e = tid + q * kBlock;
-        ar[q] = ai[q] = 0.0;
+        nr[q] = ni[q] = 0.0;
         if (e >= NN) continue;
         const int i = e / N, j = e - (e / N) * N;
+        // -i [H, sigma_0] (the damping vanishes at u = 0)
         double cr = 0, ci = 0;
         if (hc) {
             for (int k = 0; k < N; ++k) {
                 const double hr = sH[2 * (i * N + k)], hi = sH[2 * (i * N + k) + 1];
-                const double sr = sS[2 * (k * N + j)], si = sS[2 * (k * N + j) + 1];
-                const double tr = sS[2 * (i * N + k)], ti = sS[2 * (i * N + k) + 1];
+                const double xr = sS[2 * (k * N + j)], xi = sS[2 * (k * N + j) + 1];
+                const double yr = sS[2 * (i * N + k)], yi = sS[2 * (i * N + k) + 1];
                 const double gr = sH[2 * (k * N + j)], gi = sH[2 * (k * N + j) + 1];
-                cr += hr * sr - hi * si - (tr * gr - ti * gi);
-                ci += hr * si + hi * sr - (tr * gi + ti * gr);
+                cr += hr * xr - hi * xi - (yr * gr - yi * gi);
+                ci += hr * xi + hi * xr - (yr * gi + yi * gr);
             }
         } else {
             for (int k = 0; k < N; ++k) {
@@ -324,53 +381,50 @@ __global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int
             }
         }
         const double dl = (i != j) ? sDelta[i] + sDelta[j] : 0.0;
-        ar[q] = ci - dl * sS[2 * e];
-        ai[q] = -cr - dl * sS[2 * e + 1];
-    }
-    // "+" couplings to the level-1 ADOs e_l (index 1 + l), stored in T
-    if (D > 0) {
-        const NbSrc<T> nbs{J.sig0[sp.in], J.rest[sp.in], N};
-        for (int l = 0; l < W; ++l) {
-            const int s = sSite[l], nb = 1 + l;
-            const double pa = sPa[l];
-#pragma unroll
-            for (int q = 0; q < EPT; ++q) {
-                const int e = tid + q * kBlock;
-                const int i = e / N, j = e - (e / N) * N;
-                if (e < NN && i != j && (i == s || j == s)) {
-                    const bool col = (j == s);
-                    const cpx<T> x = (J.herm && col) ? cconj(load_nb<T>(nbs, nb, s, i))
-                                                     : load_nb<T>(nbs, nb, i, j);
-                    const double a = col ? -pa : pa;
-                    ar[q] -= a * (double)x.im;
-                    ai[q] += a * (double)x.re;
+        double fr = ci - dl * sS[2 * e], fi = -cr - dl * sS[2 * e + 1];
+        // "+" couplings to the level-1 ADOs e_l (index 1 + l), modes of states i and j
+        if (D > 0 && i != j) {
+            for (int pass = 0; pass < 2; ++pass) {
+                const int s = pass == 0 ? i : j;
+                for (int m = sBegin[s]; m < sBegin[s + 1]; ++m) {
+                    const int l = sModes[m];
+                    cpx<T> x;
+                    if (L.rows_in_lds) {
+                        if (pass == 0) {
+                            x = {sRows[2 * (l * N + j)], sRows[2 * (l * N + j) + 1]};
+                        } else if (herm) {
+                            x = cconj(cpx<T>{sRows[2 * (l * N + i)], sRows[2 * (l * N + i) + 1]});
+                        } else {
+                            x = {sCols[2 * (l * N + i)], sCols[2 * (l * N + i) + 1]};
+                        }
+                    } else {
+                        x = (herm && pass == 1) ? cconj(load_nb<T>(nbs, 1 + l, s, i))
+                                                : load_nb<T>(nbs, 1 + l, i, j);
+                    }
+                    const double pa = pass == 0 ? sPa[l] : -sPa[l];
+                    fr -= pa * (double)x.im;
+                    fi += pa * (double)x.re;
                 }
             }
         }
-    }
-    // RK4 stage combination in FP64
-    const double h = sp.hmul * J.dt;
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-        const int e = tid + q * kBlock;
-        if (e >= NN) continue;
+        // RK4 stage combination in FP64
         double yr = sp.w_in * sS[2 * e], yi = sp.w_in * sS[2 * e + 1];
         for (int m = 0; m < sp.nbase; ++m) {
             const cpx<double> bv = ld<double>(J.sig0[sp.base[m]], e);
             yr += sp.wbase[m] * bv.re;
             yi += sp.wbase[m] * bv.im;
         }
-        ar[q] = yr + h * ar[q];
-        ai[q] = yi + h * ai[q];
+        nr[q] = yr + h * fr;
+        ni[q] = yi + h * fi;
     }
-    __syncthreads();  // every thread has read the old tile
+    __syncthreads();  // every thread has read the old sigma_0 from LDS
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
         const int e = tid + q * kBlock;
         if (e >= NN) continue;
-        st<double>(J.sig0[sp.out], e, cpx<double>{ar[q], ai[q]});
-        sS[2 * e] = ar[q];
-        sS[2 * e + 1] = ai[q];
+        st<double>(J.sig0[sp.out], e, cpx<double>{nr[q], ni[q]});
+        sS[2 * e] = nr[q];
+        sS[2 * e + 1] = ni[q];
     }
     if (sp.record_after) {
         __syncthreads();
@@ -549,6 +603,10 @@ __device__ void fill_block_tables(const Tables& t, int u, int lev, const BlockTa
     __syncthreads();
 }
 
+// At most this many "-" neighbour rows are prefetched into LDS per ADO
+// (one element per thread for N <= 64); further links read global memory.
+constexpr int kPrefRows = 4;
+
 template <typename T, int NB, bool HERM>
 __global__ __launch_bounds__(256) void k_bulk_mfma(Job single, const Job* jobs, int n_jobs,
                                                    StageSpec sp) {
@@ -576,40 +634,28 @@ __global__ __launch_bounds__(256) void k_bulk_mfma(Job single, const Job* jobs, 
     T* sXim = sXre + PLANE;
     T* sYre = sXim + PLANE;  // general path only
     T* sYim = sYre + PLANE;
-    const BlockTables<T> bt = carve_tables<T>(reinterpret_cast<char*>(HERM ? sYre : sYim + PLANE),
-                                              N, W);
+    T* sRow = HERM ? sYre : sYim + PLANE;  // kPrefRows x NP complex (Hermitian path)
+    const BlockTables<T> bt = carve_tables<T>(
+        reinterpret_cast<char*>(HERM ? sRow + 2 * kPrefRows * NP : sRow), N, W);
 
-    // Issue the loads of the own tile and of the stage bases first.
+    // Own tile: global -> LDS planes (loads first, then the LDS writes).
     const size_t base = (size_t)(u - 1) * NN;
-    const void* in = J.rest[sp.in];
-    cpx<T> own[EPT];
-    cpx<T> acc_base[EPT];
-    int ei[EPT], ej[EPT];
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-        const int e = tid + q * kBlock;
-        ei[q] = e / N;
-        ej[q] = e - ei[q] * N;
-        own[q] = (e < NN) ? ld<T>(in, base + e) : cpx<T>{(T)0, (T)0};
-        acc_base[q] = {(T)0, (T)0};
-    }
-    for (int m = 0; m < sp.nbase; ++m) {
-        const T w = (T)sp.wbase[m];
-        const void* bp = J.rest[sp.base[m]];
+    {
+        const void* in = J.rest[sp.in];
+        cpx<T> v[EPT];
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
-            if (tid + q * kBlock < NN) {
-                const cpx<T> v = ld<T>(bp, base + tid + q * kBlock);
-                acc_base[q].re += w * v.re;
-                acc_base[q].im += w * v.im;
-            }
+            const int e = tid + q * kBlock;
+            v[q] = (e < NN) ? ld<T>(in, base + e) : cpx<T>{(T)0, (T)0};
         }
-    }
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-        if (tid + q * kBlock < NN) {
-            sSre[ei[q] * LS + ej[q]] = own[q].re;
-            sSim[ei[q] * LS + ej[q]] = own[q].im;
+        for (int q = 0; q < EPT; ++q) {
+            const int e = tid + q * kBlock;
+            if (e < NN) {
+                const int i = e / N, j = e - (e / N) * N;
+                sSre[i * LS + j] = v[q].re;
+                sSim[i * LS + j] = v[q].im;
+            }
         }
     }
     if (N < NP) {
@@ -623,74 +669,89 @@ __global__ __launch_bounds__(256) void k_bulk_mfma(Job single, const Job* jobs, 
     }
     const int lev = t.level[u];
     const T gam = (T)t.damping[u];
+    fill_block_tables<T>(t, u, lev, bt);  // ends with a barrier (also publishes the planes)
 
-    // H as the A operand: hreg[mt][ks] = H[16 mt + lane%16][4 ks + lane/16]
-    T hreg[NB][KS];
-#pragma unroll
-    for (int mt = 0; mt < NB; ++mt)
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int r = 16 * mt + (lane & 15), c = 4 * ks + (lane >> 4);
-            hreg[mt][ks] = (r < N && c < N) ? (T)t.h_re[r * N + c] : (T)0;
-        }
-    const int ksteps = (N + 3) >> 2;
-    fill_block_tables<T>(t, u, lev, bt);  // ends with a barrier (also publishes sS)
+    // Prefetch the row s of every active "-" neighbour (Hermitian path): its
+    // latency hides behind the matrix-core phase.
+    const NbSrc<T> nbs{J.sig0[sp.in], J.rest[sp.in], N};
+    const int n_minus = bt.count[4];
+    const int n_pref = HERM ? min(n_minus, kPrefRows) : 0;
+    cpx<T> pre = {(T)0, (T)0};
+    const bool has_pre = tid < n_pref * N;
+    if (has_pre) {
+        const int a = tid / N, c = tid - (tid / N) * N;
+        pre = load_nb<T>(nbs, bt.mnb[a], bt.msite[a], c);
+    }
 
-    // X = H [Re S | Im S]
+    // X = H [Re S | Im S]; H is the A operand, hreg[mt][ks] = H[16 mt + lane%16][4 ks + lane/16]
+    {
+        T hreg[NB][KS];
 #pragma unroll
-    for (int mt = 0; mt < NB; ++mt) {
-        for (int nt = ((wave - mt * NTC) % 4 + 4) % 4; nt < NTC; nt += 4) {
-            const T* plane = nt < NB ? sSre : sSim;
-            const int c0 = 16 * (nt < NB ? nt : nt - NB);
-            acc_t acc = {0, 0, 0, 0};
+        for (int mt = 0; mt < NB; ++mt)
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
-                if (ks < ksteps) {
-                    const T bv = plane[(4 * ks + (lane >> 4)) * LS + c0 + (lane & 15)];
-                    acc = mfma16(hreg[mt][ks], bv, acc);
-                }
+                const int r = 16 * mt + (lane & 15), c = 4 * ks + (lane >> 4);
+                hreg[mt][ks] = (r < N && c < N) ? (T)t.h_re[r * N + c] : (T)0;
             }
-            T* out = nt < NB ? sXre : sXim;
+        const int ksteps = (N + 3) >> 2;
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                out[(16 * mt + mfma_row<T>(lane, r)) * LS + c0 + (lane & 15)] = acc[r];
-        }
-    }
-    if (!HERM) {
-        // Y = S H (H real symmetric: the B operand H[k][j] has the A layout)
-#pragma unroll
-        for (int mt = 0; mt < 2 * NB; ++mt) {
-            const T* plane = mt < NB ? sSre : sSim;
-            const int r0 = 16 * (mt < NB ? mt : mt - NB);
-#pragma unroll
-            for (int nt = 0; nt < NB; ++nt) {
-                if (((mt * NB + nt) & 3) != wave) continue;
+        for (int mt = 0; mt < NB; ++mt) {
+            for (int nt = ((wave - mt * NTC) % 4 + 4) % 4; nt < NTC; nt += 4) {
+                const T* plane = nt < NB ? sSre : sSim;
+                const int c0 = 16 * (nt < NB ? nt : nt - NB);
                 acc_t acc = {0, 0, 0, 0};
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) {
                     if (ks < ksteps) {
-                        const T av = plane[(r0 + (lane & 15)) * LS + 4 * ks + (lane >> 4)];
-                        acc = mfma16(av, hreg[nt][ks], acc);
+                        const T bv = plane[(4 * ks + (lane >> 4)) * LS + c0 + (lane & 15)];
+                        acc = mfma16(hreg[mt][ks], bv, acc);
                     }
                 }
-                T* out = mt < NB ? sYre : sYim;
+                T* out = nt < NB ? sXre : sXim;
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    out[(r0 + mfma_row<T>(lane, r)) * LS + 16 * nt + (lane & 15)] = acc[r];
+                    out[(16 * mt + mfma_row<T>(lane, r)) * LS + c0 + (lane & 15)] = acc[r];
+            }
+        }
+        if (!HERM) {
+            // Y = S H (H real symmetric: the B operand H[k][j] has the A layout)
+#pragma unroll
+            for (int mt = 0; mt < 2 * NB; ++mt) {
+                const T* plane = mt < NB ? sSre : sSim;
+                const int r0 = 16 * (mt < NB ? mt : mt - NB);
+#pragma unroll
+                for (int nt = 0; nt < NB; ++nt) {
+                    if (((mt * NB + nt) & 3) != wave) continue;
+                    acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+                    for (int ks = 0; ks < KS; ++ks) {
+                        if (ks < ksteps) {
+                            const T av = plane[(r0 + (lane & 15)) * LS + 4 * ks + (lane >> 4)];
+                            acc = mfma16(av, hreg[nt][ks], acc);
+                        }
+                    }
+                    T* out = mt < NB ? sYre : sYim;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        out[(r0 + mfma_row<T>(lane, r)) * LS + 16 * nt + (lane & 15)] = acc[r];
+                }
             }
         }
     }
+    if (has_pre) {
+        sRow[2 * tid] = pre.re;
+        sRow[2 * tid + 1] = pre.im;
+    }
     __syncthreads();
 
-    // -i[H, sigma], damping and correction lines
-    T ar[EPT], ai[EPT];
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-        const int i = ei[q], j = ej[q];
-        if (tid + q * kBlock >= NN) {
-            ar[q] = ai[q] = (T)0;
-            continue;
-        }
+    // Elementwise lines: -i[H, sigma], damping, correction, couplings.  Each
+    // thread reads only its own elements of the sigma planes here, so the
+    // stage value w_in * sigma + h * f goes back into the same slots.
+    const float invN = 1.0f / (float)N;  // exact row index for e < 4096 (N <= 64)
+    const T h = (T)(sp.hmul * J.dt), w_in = (T)sp.w_in;
+#pragma unroll 1
+    for (int e = tid; e < NN; e += kBlock) {
+        const int i = (int)(((float)e + 0.5f) * invN), j = e - i * N;
         T cr, ci;
         if (HERM) {
             cr = sXre[i * LS + j] - sXre[j * LS + i];
@@ -699,58 +760,71 @@ __global__ __launch_bounds__(256) void k_bulk_mfma(Job single, const Job* jobs, 
             cr = sXre[i * LS + j] - sYre[i * LS + j];
             ci = sXim[i * LS + j] - sYim[i * LS + j];
         }
-        const T dl = (i != j) ? bt.delta[i] + bt.delta[j] : (T)0;
-        ar[q] = ci - (gam + dl) * own[q].re;
-        ai[q] = -cr - (gam + dl) * own[q].im;
-    }
-    // coupling lines: links outermost, the thread's elements innermost
-    const NbSrc<T> nbs{J.sig0[sp.in], J.rest[sp.in], N};
-    const int n_minus = bt.count[4];
-    for (int a = 0; a < n_minus; ++a) {
-        const int s = bt.msite[a], nb = bt.mnb[a];
-        const T ml = bt.mml[a], mc = bt.mmc[a];
-#pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-            const int i = ei[q], j = ej[q];
-            if (tid + q * kBlock < NN && (i == s || j == s)) {
-                const bool col = (j == s) && (i != s);
-                const cpx<T> x = (HERM && col) ? cconj(load_nb<T>(nbs, nb, s, i))
-                                               : load_nb<T>(nbs, nb, i, j);
-                const T vx = (T)((i == s) - (j == s)), vo = (T)((i == s) + (j == s));
-                const T thr = ml * vo, thi = mc * vx;
-                ar[q] += thr * x.re - thi * x.im;
-                ai[q] += thr * x.im + thi * x.re;
+        const T sr = sSre[i * LS + j], si = sSim[i * LS + j];
+        const T g = gam + ((i != j) ? bt.delta[i] + bt.delta[j] : (T)0);
+        T fr = ci - g * sr, fi = -cr - g * si;
+        for (int a = 0; a < n_minus; ++a) {
+            const int s = bt.msite[a];
+            if (i != s && j != s) continue;
+            const bool col = (j == s) && (i != s);
+            cpx<T> x;
+            if (a < n_pref) {
+                const int c = col ? i : j;  // Hermitian: column s is conj(row s)
+                x = {sRow[2 * (a * N + c)], sRow[2 * (a * N + c) + 1]};
+                if (col) x = cconj(x);
+            } else {
+                x = (HERM && col) ? cconj(load_nb<T>(nbs, bt.mnb[a], s, i))
+                                  : load_nb<T>(nbs, bt.mnb[a], i, j);
             }
+            const T vx = (T)((i == s) - (j == s)), vo = (T)((i == s) + (j == s));
+            const T thr = bt.mml[a] * vo, thi = bt.mmc[a] * vx;
+            fr += thr * x.re - thi * x.im;
+            fi += thr * x.im + thi * x.re;
         }
-    }
-    if (lev < D) {
-        for (int l = 0; l < W; ++l) {
-            const int s = bt.site[l], nb = bt.pnb[l];
-            const T pa = bt.pa[l];
-#pragma unroll
-            for (int q = 0; q < EPT; ++q) {
-                const int i = ei[q], j = ej[q];
-                if (tid + q * kBlock < NN && i != j && (i == s || j == s)) {
-                    const bool col = (j == s);
-                    const cpx<T> x = (HERM && col) ? cconj(load_nb<T>(nbs, nb, s, i))
-                                                   : load_nb<T>(nbs, nb, i, j);
-                    const T a = col ? -pa : pa;  // i * pa * vx * x
-                    ar[q] -= a * x.im;
-                    ai[q] += a * x.re;
+        if (lev < D && i != j) {
+            for (int pass = 0; pass < 2; ++pass) {
+                const int s = pass == 0 ? i : j;
+                for (int m = t.state_mode_begin[s]; m < t.state_mode_begin[s + 1]; ++m) {
+                    const int l = t.state_modes[m];
+                    const int nb = bt.pnb[l];
+                    const cpx<T> x = (HERM && pass == 1) ? cconj(load_nb<T>(nbs, nb, s, i))
+                                                         : load_nb<T>(nbs, nb, i, j);
+                    const T pa = pass == 0 ? bt.pa[l] : -bt.pa[l];  // i * pa * vx * x
+                    fr -= pa * x.im;
+                    fi += pa * x.re;
                 }
             }
         }
+        sSre[i * LS + j] = w_in * sr + h * fr;
+        sSim[i * LS + j] = w_in * si + h * fi;
     }
-    // RK4 stage combination
-    const T h = (T)(sp.hmul * J.dt);
-    const T w_in = (T)sp.w_in;
+    // RK4 stage combination: per base array, every load first, then the sums.
+    for (int m = 0; m < sp.nbase; ++m) {
+        const T w = (T)sp.wbase[m];
+        const void* bp = J.rest[sp.base[m]];
+        cpx<T> v[EPT];
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int e = tid + q * kBlock;
+            v[q] = (e < NN) ? ld<T>(bp, base + e) : cpx<T>{(T)0, (T)0};
+        }
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int e = tid + q * kBlock;
+            if (e < NN) {
+                const int i = (int)(((float)e + 0.5f) * invN), j = e - i * N;
+                sSre[i * LS + j] += w * v[q].re;
+                sSim[i * LS + j] += w * v[q].im;
+            }
+        }
+    }
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
         const int e = tid + q * kBlock;
-        if (e >= NN) continue;
-        const T yr = w_in * own[q].re + acc_base[q].re + h * ar[q];
-        const T yi = w_in * own[q].im + acc_base[q].im + h * ai[q];
-        st<T>(J.rest[sp.out], base + e, cpx<T>{yr, yi});
+        if (e < NN) {
+            const int i = (int)(((float)e + 0.5f) * invN), j = e - i * N;
+            st<T>(J.rest[sp.out], base + e, cpx<T>{sSre[i * LS + j], sSim[i * LS + j]});
+        }
     }
 }
 
@@ -758,8 +832,8 @@ template <typename T, int NB, bool HERM>
 size_t mfma_lds_bytes(int N, int W) {
     constexpr int NP = 16 * NB;
     constexpr int LS = NP + 1;
-    return sizeof(T) * (size_t)NP * LS * (HERM ? 4 : 6) + (size_t)W * (4 * 4 + 3 * sizeof(T)) +
-           (size_t)N * sizeof(T) + 8 * 4;
+    return sizeof(T) * ((size_t)NP * LS * (HERM ? 4 : 6) + (HERM ? 2 * kPrefRows * NP : 0)) +
+           (size_t)W * (4 * 4 + 3 * sizeof(T)) + (size_t)N * sizeof(T) + 8 * 4;
 }
 
 }  // namespace
@@ -826,24 +900,42 @@ static hipError_t launch_stage_t(const Job& single, const Job* jobs_dev, int n_j
                                  int total_tiles, const StageSpec& sp, hipStream_t stream,
                                  hipEvent_t ev_begin, hipEvent_t ev_end) {
     const int N = single.t.N;
-    const int NN = N * N;
-    // sigma_0: FP64 LDS for H, sigma_0, per-mode weights and sites, per-state delta
-    const size_t lds0 = 4 * (size_t)NN * sizeof(double) + (size_t)single.t.W * 12 +
-                        (size_t)N * sizeof(double);
     // Allow dynamic LDS above 64 KiB (N up to 64 in FP64).
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sigma0<T>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (a == hipSuccess)
-            a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bulk_fma<T>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipError_t a = hipSuccess;
+        const void* fns[5] = {reinterpret_cast<const void*>(&k_sigma0<T, 1>),
+                              reinterpret_cast<const void*>(&k_sigma0<T, 2>),
+                              reinterpret_cast<const void*>(&k_sigma0<T, 3>),
+                              reinterpret_cast<const void*>(&k_sigma0<T, 4>),
+                              reinterpret_cast<const void*>(&k_bulk_fma<T>)};
+        for (const void* f : fns)
+            if (a == hipSuccess)
+                a = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (a != hipSuccess) return a;
         attr_set = true;
     }
     const int n0 = jobs_dev ? n_jobs : 1;
-    hipLaunchKernelGGL(k_sigma0<T>, dim3(n0), dim3(kBlock), lds0, stream, single, jobs_dev, n_jobs,
-                       sp);
+    // largest N and W of the batch; non-Hermitian staging needs the most
+    const size_t lds0 = sigma0_lds(N, single.t.W, (int)sizeof(T), false, 160 * 1024).total;
+    switch ((N + 15) / 16) {
+        case 1:
+            hipLaunchKernelGGL((k_sigma0<T, 1>), dim3(n0), dim3(kBlock), lds0, stream, single,
+                               jobs_dev, n_jobs, sp, (unsigned)lds0);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_sigma0<T, 2>), dim3(n0), dim3(kBlock), lds0, stream, single,
+                               jobs_dev, n_jobs, sp, (unsigned)lds0);
+            break;
+        case 3:
+            hipLaunchKernelGGL((k_sigma0<T, 3>), dim3(n0), dim3(kBlock), lds0, stream, single,
+                               jobs_dev, n_jobs, sp, (unsigned)lds0);
+            break;
+        default:
+            hipLaunchKernelGGL((k_sigma0<T, 4>), dim3(n0), dim3(kBlock), lds0, stream, single,
+                               jobs_dev, n_jobs, sp, (unsigned)lds0);
+            break;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || total_tiles == 0) return e;
     // MFMA path for 16 <= N (real H); FP64 above N = 48 would need more than
