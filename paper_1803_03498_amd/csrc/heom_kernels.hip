@@ -27,20 +27,39 @@ __device__ __forceinline__ cpx<T> cconj(cpx<T> a) {
     return {a.re, -a.im};
 }
 
+// (re, im) pairs as clang vector types: one 8- or 16-byte access per element.
+typedef float pair_f __attribute__((ext_vector_type(2)));
+typedef double pair_d __attribute__((ext_vector_type(2)));
 template <typename T>
 struct vec2;
 template <>
 struct vec2<float> {
-    using type = float2;
+    using type = pair_f;
 };
 template <>
 struct vec2<double> {
-    using type = double2;
+    using type = pair_d;
 };
+
+// Global-memory views of pointers held in descriptors.  Without the cast the
+// compiler cannot prove these generic pointers are global and emits FLAT
+// instructions, whose completion is tracked together with LDS traffic.
+template <typename T>
+using gcptr = const __attribute__((address_space(1))) T*;
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gcptr<T> G(const T* p) {
+    return (gcptr<T>)p;
+}
+template <typename T>
+__device__ __forceinline__ gptr<T> G(T* p) {
+    return (gptr<T>)p;
+}
 
 template <typename T>
 __device__ __forceinline__ cpx<T> ld(const void* base, size_t idx) {
-    typename vec2<T>::type v = reinterpret_cast<const typename vec2<T>::type*>(base)[idx];
+    typename vec2<T>::type v = G(reinterpret_cast<const typename vec2<T>::type*>(base))[idx];
     return {v.x, v.y};
 }
 
@@ -49,7 +68,7 @@ __device__ __forceinline__ void st(void* base, size_t idx, cpx<T> a) {
     typename vec2<T>::type v;
     v.x = a.re;
     v.y = a.im;
-    reinterpret_cast<typename vec2<T>::type*>(base)[idx] = v;
+    G(reinterpret_cast<typename vec2<T>::type*>(base))[idx] = v;
 }
 
 // --------------------------------------------------------------------------
@@ -59,7 +78,7 @@ __device__ __forceinline__ void st(void* base, size_t idx, cpx<T> a) {
 //   rank(n)  = start(|n|) + sum_{i<W-1, R_i>n_i} C(R_i-n_i-1+W-1-i, W-1-i),
 //              R_i = |n| - sum_{j<i} n_j  (tuples with a larger n_i come first)
 // --------------------------------------------------------------------------
-__device__ int64_t rank_with(const uint8_t* n, int W, const int64_t* binom, int l, int delta) {
+__device__ int64_t rank_with(gcptr<uint8_t> n, int W, gcptr<int64_t> binom, int l, int delta) {
     int L = delta;
     for (int i = 0; i < W; ++i) L += n[i];
     const int ks = W + 1;
@@ -78,16 +97,16 @@ __global__ __launch_bounds__(256) void k_enumerate(Tables t) {
     if (u >= t.n_ado) return;
     const int W = t.W, D = t.D;
     const int ks = W + 1;
-    uint8_t* n = t.tuples + (size_t)u * W;
+    gptr<uint8_t> n = G(t.tuples) + (size_t)u * W;
     // level: smallest L with u < C(W+L, W)
     int L = 0;
-    while (L < D && (int64_t)u >= t.binom[(size_t)L * ks + W]) ++L;
-    int64_t r = u - ((L == 0) ? 0 : t.binom[(size_t)(L - 1) * ks + W]);
+    while (L < D && (int64_t)u >= G(t.binom)[(size_t)L * ks + W]) ++L;
+    int64_t r = u - ((L == 0) ? 0 : G(t.binom)[(size_t)(L - 1) * ks + W]);
     int R = L;
     for (int i = 0; i < W - 1; ++i) {
         int v = R;
         for (; v > 0; --v) {
-            const int64_t cnt = t.binom[(size_t)(R - v) * ks + (W - 2 - i)];
+            const int64_t cnt = G(t.binom)[(size_t)(R - v) * ks + (W - 2 - i)];
             if (r < cnt) break;
             r -= cnt;
         }
@@ -95,10 +114,10 @@ __global__ __launch_bounds__(256) void k_enumerate(Tables t) {
         R -= v;
     }
     if (W > 0) n[W - 1] = (uint8_t)R;
-    t.level[u] = (uint8_t)L;
+    G(t.level)[u] = (uint8_t)L;
     double damp = 0.0;
-    for (int l = 0; l < W; ++l) damp += n[l] * t.mode_gamma[l];
-    t.damping[u] = damp;
+    for (int l = 0; l < W; ++l) damp += n[l] * G(t.mode_gamma)[l];
+    G(t.damping)[u] = damp;
 }
 
 // One thread per (u, l): the "+" link (valid while |n| < D) and the "-" link
@@ -109,9 +128,9 @@ __global__ __launch_bounds__(256) void k_links(Tables t) {
     if (idx >= (int64_t)t.n_ado * W) return;
     const int u = (int)(idx / W);
     const int l = (int)(idx - (int64_t)u * W);
-    const uint8_t* n = t.tuples + (size_t)u * W;
-    t.plus[idx] = (t.level[u] < t.D) ? (int32_t)rank_with(n, W, t.binom, l, +1) : -1;
-    t.minus[idx] = (n[l] > 0) ? (int32_t)rank_with(n, W, t.binom, l, -1) : -1;
+    const gptr<uint8_t> n = G(t.tuples) + (size_t)u * W;
+    G(t.plus)[idx] = (G(t.level)[u] < t.D) ? (int32_t)rank_with(n, W, G(t.binom), l, +1) : -1;
+    G(t.minus)[idx] = (n[l] > 0) ? (int32_t)rank_with(n, W, G(t.binom), l, -1) : -1;
 }
 
 // --------------------------------------------------------------------------
@@ -159,41 +178,41 @@ __device__ __forceinline__ cpx<T> rhs_element(const Tables& t, const T* sH, cons
     const T s_r = sS[2 * (i * N + j)], s_i = sS[2 * (i * N + j) + 1];
     T ar = ci, ai = -cr;  // -i * comm
     // second line: damping
-    const T gam = (T)t.damping[u];
+    const T gam = (T)G(t.damping)[u];
     ar -= gam * s_r;
     ai -= gam * s_i;
     // third line: correction term, (1 - d_ij)(Delta_i + Delta_j)
     if (i != j) {
-        const T dl = (T)(t.delta_state[i] + t.delta_state[j]);
+        const T dl = (T)(G(t.delta_state)[i] + G(t.delta_state)[j]);
         ar -= dl * s_r;
         ai -= dl * s_i;
     }
-    const int lev = (u == 0) ? 0 : t.level[u];
-    const uint8_t* nu_ = t.tuples + (size_t)u * W;
+    const int lev = (u == 0) ? 0 : G(t.level)[u];
+    gcptr<uint8_t> nu_ = G(t.tuples) + (size_t)u * W;
     const int npass = (i == j) ? 1 : 2;
     for (int pass = 0; pass < npass; ++pass) {
         const int s = pass == 0 ? i : j;
         const T vx = (T)((i == s) - (j == s));
         const T vo = (T)((i == s) + (j == s));
         const bool col = (j == s) && (i != s);
-        for (int m = t.state_mode_begin[s]; m < t.state_mode_begin[s + 1]; ++m) {
-            const int l = t.state_modes[m];
+        for (int m = G(t.state_mode_begin)[s]; m < G(t.state_mode_begin)[s + 1]; ++m) {
+            const int l = G(t.state_modes)[m];
             const int nl = nu_[l];
             if (lev < D && i != j) {
-                const int nb = t.plus[(size_t)u * W + l];
+                const int nb = G(t.plus)[(size_t)u * W + l];
                 const cpx<T> x = (herm && col) ? cconj(load_nb<T>(nbs, nb, j, i))
                                                : load_nb<T>(nbs, nb, i, j);
-                const T a = (T)t.plus_coef[l * (D + 1) + nl] * vx;
+                const T a = (T)G(t.plus_coef)[l * (D + 1) + nl] * vx;
                 ar -= a * x.im;  // i * a * x
                 ai += a * x.re;
             }
             if (nl > 0) {
-                const int nb = t.minus[(size_t)u * W + l];
+                const int nb = G(t.minus)[(size_t)u * W + l];
                 const cpx<T> x = (herm && col) ? cconj(load_nb<T>(nbs, nb, j, i))
                                                : load_nb<T>(nbs, nb, i, j);
-                const T b = (T)t.minus_coef[l * (D + 1) + nl];
-                const T thr = b * (T)t.mode_lamnu[l] * vo;  // real part of b*theta
-                const T thi = b * (T)t.mode_c[l] * vx;      // imaginary part
+                const T b = (T)G(t.minus_coef)[l * (D + 1) + nl];
+                const T thr = b * (T)G(t.mode_lamnu)[l] * vo;  // real part of b*theta
+                const T thi = b * (T)G(t.mode_c)[l] * vx;      // imaginary part
                 ar += thr * x.re - thi * x.im;
                 ai += thr * x.im + thi * x.re;
             }
@@ -210,19 +229,33 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return x * per + (x < rem ? x : rem) + idx;
 }
 
-__device__ __forceinline__ const Job& find_job(const Job& single, const Job* jobs, int n_jobs,
-                                               int tile) {
-    if (jobs == nullptr) return single;
-    int lo = 0, hi = n_jobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].tile_begin <= tile)
-            lo = mid;
-        else
-            hi = mid - 1;
+// The job a tile belongs to.  Single-job launches read the descriptor from
+// the kernel argument; batched launches from the device job table (found by
+// binary search over the jobs' first tiles).  Keeping the two apart lets the
+// compiler address each descriptor in its own memory space.
+template <bool BATCHED>
+struct JobOf;
+template <>
+struct JobOf<false> {
+    static __device__ __forceinline__ const Job& get(const Job& single, const Job*, int, int) {
+        return single;
     }
-    return jobs[lo];
-}
+};
+template <>
+struct JobOf<true> {
+    static __device__ __forceinline__ const Job& get(const Job&, const Job* jobs, int n_jobs,
+                                                     int tile) {
+        int lo = 0, hi = n_jobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].tile_begin <= tile)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        return jobs[lo];
+    }
+};
 
 // --------------------------------------------------------------------------
 // sigma_0 stage kernel: one workgroup per job, FP64 throughout; reads the
@@ -232,7 +265,7 @@ __device__ void record_sigma0(const Job& J, const double* sS, int64_t slot) {
     // sS: interleaved complex128 [N][N] in LDS.  Caller: one thread.
     if (slot < 0 || slot >= J.n_rec_max) return;
     const int N = J.t.N;
-    double* rec = J.records + slot * J.rec_doubles;
+    gptr<double> rec = G(J.records) + slot * J.rec_doubles;
     double trr = 0.0, tri = 0.0;
     for (int i = 0; i < N; ++i) {
         trr += sS[2 * (i * N + i)];
@@ -256,8 +289,8 @@ __device__ void record_sigma0(const Job& J, const double* sS, int64_t slot) {
     } else {
         double pr = 0.0, pi = 0.0;
         for (int a = 0; a < N; ++a) {
-            pr += J.mu[a] * sS[2 * (a * N + J.ground)];
-            pi += J.mu[a] * sS[2 * (a * N + J.ground) + 1];
+            pr += G(J.mu)[a] * sS[2 * (a * N + J.ground)];
+            pi += G(J.mu)[a] * sS[2 * (a * N + J.ground) + 1];
         }
         rec[0] = pr;
         rec[1] = pi;
@@ -265,7 +298,7 @@ __device__ void record_sigma0(const Job& J, const double* sS, int64_t slot) {
         rec[3] = tri;
         finite = finite && isfinite(pr) && isfinite(pi);
     }
-    if (!finite) *J.status = 1;
+    if (!finite) *G(J.status) = 1;
 }
 
 // LDS plan of the sigma_0 kernel: H and sigma_0 in FP64, per-mode weights,
@@ -299,11 +332,11 @@ __host__ __device__ inline Sigma0Lds sigma0_lds(int N, int W, int tsize, bool he
     return L;
 }
 
-template <typename T, int NB>
+template <typename T, int NB, bool BATCHED>
 __global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int n_jobs,
                                                 StageSpec sp, unsigned lds_cap) {
     constexpr int EPT = (16 * NB * 16 * NB + kBlock - 1) / kBlock;
-    const Job& J = (jobs == nullptr) ? single : jobs[blockIdx.x];
+    const Job& J = BATCHED ? jobs[blockIdx.x] : single;
     const Tables& t = J.t;
     const int N = t.N, NN = N * N, W = t.W, D = t.D;
     const bool herm = J.herm != 0;
@@ -322,25 +355,25 @@ __global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int
     const bool hc = t.h_complex != 0;
     const NbSrc<T> nbs{J.sig0[sp.in], J.rest[sp.in], N};
     for (int e = tid; e < NN; e += blockDim.x) {
-        sH[2 * e] = t.h_re[e];
-        sH[2 * e + 1] = hc ? t.h_im[e] : 0.0;
+        sH[2 * e] = G(t.h_re)[e];
+        sH[2 * e + 1] = hc ? G(t.h_im)[e] : 0.0;
         const cpx<double> v = ld<double>(J.sig0[sp.in], e);
         sS[2 * e] = v.re;
         sS[2 * e + 1] = v.im;
     }
     for (int l = tid; l < W; l += blockDim.x) {
-        sPa[l] = (D > 0) ? t.plus_coef[l * (D + 1)] : 0.0;
-        sSite[l] = t.mode_site[l];
-        sModes[l] = t.state_modes[l];
+        sPa[l] = (D > 0) ? G(t.plus_coef)[l * (D + 1)] : 0.0;
+        sSite[l] = G(t.mode_site)[l];
+        sModes[l] = G(t.state_modes)[l];
     }
     for (int x = tid; x <= N; x += blockDim.x) {
-        sBegin[x] = t.state_mode_begin[x];
-        if (x < N) sDelta[x] = t.delta_state[x];
+        sBegin[x] = G(t.state_mode_begin)[x];
+        if (x < N) sDelta[x] = G(t.delta_state)[x];
     }
     if (D > 0 && L.rows_in_lds) {
         for (int idx = tid; idx < W * N; idx += blockDim.x) {
             const int l = idx / N, c = idx - (idx / N) * N;
-            const int site = t.mode_site[l];
+            const int site = G(t.mode_site)[l];
             const cpx<T> r = load_nb<T>(nbs, 1 + l, site, c);
             sRows[2 * idx] = r.re;
             sRows[2 * idx + 1] = r.im;
@@ -352,7 +385,7 @@ __global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int
         }
     }
     __syncthreads();
-    if (sp.record_initial && tid == 0 && *J.step == 0) record_sigma0(J, sS, 0);
+    if (sp.record_initial && tid == 0 && *G(J.step) == 0) record_sigma0(J, sS, 0);
 
     double nr[EPT], ni[EPT];
     const double h = sp.hmul * J.dt;
@@ -429,8 +462,8 @@ __global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int
     if (sp.record_after) {
         __syncthreads();
         if (tid == 0) {
-            const int64_t step = *J.step + 1;
-            *J.step = step;
+            const int64_t step = *G(J.step) + 1;
+            *G(J.step) = step;
             if (step % J.rec_every == 0) record_sigma0(J, sS, step / J.rec_every);
         }
     }
@@ -440,22 +473,22 @@ __global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int
 // Bulk stage kernel, wavefront-FMA path: a workgroup takes G consecutive ADOs
 // (G = max(1, 256 / N^2)); every thread owns whole matrix elements.
 // --------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool BATCHED>
 __global__ __launch_bounds__(256) void k_bulk_fma(Job single, const Job* jobs, int n_jobs,
                                                   StageSpec sp) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const Job& J = find_job(single, jobs, n_jobs, b);
+    const Job& J = JobOf<BATCHED>::get(single, jobs, n_jobs, b);
     const Tables& t = J.t;
-    const int N = t.N, NN = N * N, G = J.ados_per_tile;
-    const int u0 = 1 + (b - J.tile_begin) * G;
-    const int n_here = min(G, t.n_ado - u0);
+    const int N = t.N, NN = N * N, GA = J.ados_per_tile;
+    const int u0 = 1 + (b - J.tile_begin) * GA;
+    const int n_here = min(GA, t.n_ado - u0);
     extern __shared__ char smem_raw[];
     T* sH = reinterpret_cast<T*>(smem_raw);  // 2*NN
-    T* sS = sH + 2 * NN;                      // 2*G*NN
+    T* sS = sH + 2 * NN;                      // 2*GA*NN
     const int tid = threadIdx.x;
     for (int e = tid; e < NN; e += blockDim.x) {
-        sH[2 * e] = (T)t.h_re[e];
-        sH[2 * e + 1] = t.h_complex ? (T)t.h_im[e] : (T)0;
+        sH[2 * e] = (T)G(t.h_re)[e];
+        sH[2 * e + 1] = t.h_complex ? (T)G(t.h_im)[e] : (T)0;
     }
     const size_t base = (size_t)(u0 - 1) * NN;
     const int tot = n_here * NN;
@@ -577,14 +610,14 @@ template <typename T>
 __device__ void fill_block_tables(const Tables& t, int u, int lev, const BlockTables<T>& b) {
     const int W = t.W, D = t.D, N = t.N;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int s = tid; s < N; s += blockDim.x) b.delta[s] = (T)t.delta_state[s];
+    for (int s = tid; s < N; s += blockDim.x) b.delta[s] = (T)G(t.delta_state)[s];
     const int l = tid;
     int nl = 0;
     if (l < W) {
-        nl = t.tuples[(size_t)u * W + l];
-        b.site[l] = t.mode_site[l];
-        b.pnb[l] = (lev < D) ? t.plus[(size_t)u * W + l] : -1;
-        b.pa[l] = (T)t.plus_coef[l * (D + 1) + nl];
+        nl = G(t.tuples)[(size_t)u * W + l];
+        b.site[l] = G(t.mode_site)[l];
+        b.pnb[l] = (lev < D) ? G(t.plus)[(size_t)u * W + l] : -1;
+        b.pa[l] = (T)G(t.plus_coef)[l * (D + 1) + nl];
     }
     const bool act = (l < W) && nl > 0;
     const unsigned long long mask = __ballot(act);
@@ -593,11 +626,11 @@ __device__ void fill_block_tables(const Tables& t, int u, int lev, const BlockTa
     if (act) {
         int slot = __popcll(mask & ((1ull << lane) - 1));
         for (int w = 0; w < wave; ++w) slot += b.count[w];
-        const double coef = t.minus_coef[l * (D + 1) + nl];
-        b.msite[slot] = t.mode_site[l];
-        b.mnb[slot] = t.minus[(size_t)u * W + l];
-        b.mml[slot] = (T)(coef * t.mode_lamnu[l]);
-        b.mmc[slot] = (T)(coef * t.mode_c[l]);
+        const double coef = G(t.minus_coef)[l * (D + 1) + nl];
+        b.msite[slot] = G(t.mode_site)[l];
+        b.mnb[slot] = G(t.minus)[(size_t)u * W + l];
+        b.mml[slot] = (T)(coef * G(t.mode_lamnu)[l]);
+        b.mmc[slot] = (T)(coef * G(t.mode_c)[l]);
     }
     if (tid == 0) b.count[4] = b.count[0] + b.count[1] + b.count[2] + b.count[3];
     __syncthreads();
@@ -607,7 +640,7 @@ __device__ void fill_block_tables(const Tables& t, int u, int lev, const BlockTa
 // (one element per thread for N <= 64); further links read global memory.
 constexpr int kPrefRows = 4;
 
-template <typename T, int NB, bool HERM>
+template <typename T, int NB, bool HERM, bool BATCHED>
 __global__ __launch_bounds__(256) void k_bulk_mfma(Job single, const Job* jobs, int n_jobs,
                                                    StageSpec sp) {
     constexpr int NP = 16 * NB;                           // padded matrix dimension
@@ -620,7 +653,7 @@ __global__ __launch_bounds__(256) void k_bulk_mfma(Job single, const Job* jobs, 
     using acc_t = typename mfma_acc<T>::type;
 
     const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const Job& J = find_job(single, jobs, n_jobs, b);
+    const Job& J = JobOf<BATCHED>::get(single, jobs, n_jobs, b);
     const Tables& t = J.t;
     const int N = t.N, NN = N * N, W = t.W, D = t.D;
     const int u = 1 + (b - J.tile_begin);
@@ -667,8 +700,8 @@ __global__ __launch_bounds__(256) void k_bulk_mfma(Job single, const Job* jobs, 
             }
         }
     }
-    const int lev = t.level[u];
-    const T gam = (T)t.damping[u];
+    const int lev = G(t.level)[u];
+    const T gam = (T)G(t.damping)[u];
     fill_block_tables<T>(t, u, lev, bt);  // ends with a barrier (also publishes the planes)
 
     // Prefetch the row s of every active "-" neighbour (Hermitian path): its
@@ -691,7 +724,7 @@ __global__ __launch_bounds__(256) void k_bulk_mfma(Job single, const Job* jobs, 
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
                 const int r = 16 * mt + (lane & 15), c = 4 * ks + (lane >> 4);
-                hreg[mt][ks] = (r < N && c < N) ? (T)t.h_re[r * N + c] : (T)0;
+                hreg[mt][ks] = (r < N && c < N) ? (T)G(t.h_re)[r * N + c] : (T)0;
             }
         const int ksteps = (N + 3) >> 2;
 #pragma unroll
@@ -784,8 +817,8 @@ __global__ __launch_bounds__(256) void k_bulk_mfma(Job single, const Job* jobs, 
         if (lev < D && i != j) {
             for (int pass = 0; pass < 2; ++pass) {
                 const int s = pass == 0 ? i : j;
-                for (int m = t.state_mode_begin[s]; m < t.state_mode_begin[s + 1]; ++m) {
-                    const int l = t.state_modes[m];
+                for (int m = G(t.state_mode_begin)[s]; m < G(t.state_mode_begin)[s + 1]; ++m) {
+                    const int l = G(t.state_modes)[m];
                     const int nb = bt.pnb[l];
                     const cpx<T> x = (HERM && pass == 1) ? cconj(load_nb<T>(nbs, nb, s, i))
                                                          : load_nb<T>(nbs, nb, i, j);
@@ -858,41 +891,81 @@ hipError_t launch_enumerate(const Tables& t, hipStream_t stream) {
     return hipGetLastError();
 }
 
-template <typename T, int NB, bool HERM>
+template <typename T, int NB, bool HERM, bool BATCHED>
 static hipError_t launch_mfma_t(const Job& single, const Job* jobs_dev, int n_jobs,
                                 int total_tiles, const StageSpec& sp, hipStream_t stream) {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bulk_mfma<T, NB, HERM>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipError_t a = hipFuncSetAttribute(
+            reinterpret_cast<const void*>(&k_bulk_mfma<T, NB, HERM, BATCHED>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (a != hipSuccess) return a;
         attr_set = true;
     }
     const size_t lds = mfma_lds_bytes<T, NB, HERM>(single.t.N, single.t.W);
-    hipLaunchKernelGGL((k_bulk_mfma<T, NB, HERM>), dim3(total_tiles), dim3(kBlock), lds, stream,
-                       single, jobs_dev, n_jobs, sp);
+    hipLaunchKernelGGL((k_bulk_mfma<T, NB, HERM, BATCHED>), dim3(total_tiles), dim3(kBlock), lds,
+                       stream, single, jobs_dev, n_jobs, sp);
     return hipGetLastError();
+}
+
+template <typename T, int NB>
+static hipError_t launch_mfma_nb(bool herm, bool batched, const Job& single, const Job* jobs_dev,
+                                 int n_jobs, int total_tiles, const StageSpec& sp,
+                                 hipStream_t stream) {
+    if (herm)
+        return batched ? launch_mfma_t<T, NB, true, true>(single, jobs_dev, n_jobs, total_tiles, sp,
+                                                          stream)
+                       : launch_mfma_t<T, NB, true, false>(single, jobs_dev, n_jobs, total_tiles,
+                                                           sp, stream);
+    return batched ? launch_mfma_t<T, NB, false, true>(single, jobs_dev, n_jobs, total_tiles, sp,
+                                                       stream)
+                   : launch_mfma_t<T, NB, false, false>(single, jobs_dev, n_jobs, total_tiles, sp,
+                                                        stream);
 }
 
 template <typename T>
 static hipError_t launch_mfma(int nb, bool herm, const Job& single, const Job* jobs_dev,
                               int n_jobs, int total_tiles, const StageSpec& sp,
                               hipStream_t stream) {
-#define HEOM_MFMA_CASE(NBV)                                                                   \
-    case NBV:                                                                                 \
-        return herm ? launch_mfma_t<T, NBV, true>(single, jobs_dev, n_jobs, total_tiles, sp,  \
-                                                  stream)                                     \
-                    : launch_mfma_t<T, NBV, false>(single, jobs_dev, n_jobs, total_tiles, sp, \
-                                                   stream);
+    const bool batched = jobs_dev != nullptr;
     switch (nb) {
-        HEOM_MFMA_CASE(1)
-        HEOM_MFMA_CASE(2)
-        HEOM_MFMA_CASE(3)
-        HEOM_MFMA_CASE(4)
-        default:
-            return hipErrorInvalidValue;
+        case 1: return launch_mfma_nb<T, 1>(herm, batched, single, jobs_dev, n_jobs, total_tiles, sp, stream);
+        case 2: return launch_mfma_nb<T, 2>(herm, batched, single, jobs_dev, n_jobs, total_tiles, sp, stream);
+        case 3: return launch_mfma_nb<T, 3>(herm, batched, single, jobs_dev, n_jobs, total_tiles, sp, stream);
+        case 4: return launch_mfma_nb<T, 4>(herm, batched, single, jobs_dev, n_jobs, total_tiles, sp, stream);
+        default: return hipErrorInvalidValue;
     }
-#undef HEOM_MFMA_CASE
+}
+
+template <typename T, int NB, bool BATCHED>
+static hipError_t launch_sigma0_t(const Job& single, const Job* jobs_dev, int n_jobs,
+                                  const StageSpec& sp, size_t lds, hipStream_t stream) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sigma0<T, NB, BATCHED>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (a != hipSuccess) return a;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_sigma0<T, NB, BATCHED>), dim3(BATCHED ? n_jobs : 1), dim3(kBlock), lds,
+                       stream, single, jobs_dev, n_jobs, sp, (unsigned)lds);
+    return hipGetLastError();
+}
+
+template <typename T, bool BATCHED>
+static hipError_t launch_fma_t(const Job& single, const Job* jobs_dev, int n_jobs,
+                               int total_tiles, const StageSpec& sp, size_t lds,
+                               hipStream_t stream) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bulk_fma<T, BATCHED>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (a != hipSuccess) return a;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_bulk_fma<T, BATCHED>), dim3(total_tiles), dim3(kBlock), lds, stream,
+                       single, jobs_dev, n_jobs, sp);
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -900,66 +973,46 @@ static hipError_t launch_stage_t(const Job& single, const Job* jobs_dev, int n_j
                                  int total_tiles, const StageSpec& sp, hipStream_t stream,
                                  hipEvent_t ev_begin, hipEvent_t ev_end) {
     const int N = single.t.N;
-    // Allow dynamic LDS above 64 KiB (N up to 64 in FP64).
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t a = hipSuccess;
-        const void* fns[5] = {reinterpret_cast<const void*>(&k_sigma0<T, 1>),
-                              reinterpret_cast<const void*>(&k_sigma0<T, 2>),
-                              reinterpret_cast<const void*>(&k_sigma0<T, 3>),
-                              reinterpret_cast<const void*>(&k_sigma0<T, 4>),
-                              reinterpret_cast<const void*>(&k_bulk_fma<T>)};
-        for (const void* f : fns)
-            if (a == hipSuccess)
-                a = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (a != hipSuccess) return a;
-        attr_set = true;
-    }
-    const int n0 = jobs_dev ? n_jobs : 1;
-    // largest N and W of the batch; non-Hermitian staging needs the most
+    const bool batched = jobs_dev != nullptr;
+    // sigma_0: largest N and W of the batch; non-Hermitian staging needs the most LDS
     const size_t lds0 = sigma0_lds(N, single.t.W, (int)sizeof(T), false, 160 * 1024).total;
+    hipError_t e;
     switch ((N + 15) / 16) {
         case 1:
-            hipLaunchKernelGGL((k_sigma0<T, 1>), dim3(n0), dim3(kBlock), lds0, stream, single,
-                               jobs_dev, n_jobs, sp, (unsigned)lds0);
+            e = batched ? launch_sigma0_t<T, 1, true>(single, jobs_dev, n_jobs, sp, lds0, stream)
+                        : launch_sigma0_t<T, 1, false>(single, jobs_dev, n_jobs, sp, lds0, stream);
             break;
         case 2:
-            hipLaunchKernelGGL((k_sigma0<T, 2>), dim3(n0), dim3(kBlock), lds0, stream, single,
-                               jobs_dev, n_jobs, sp, (unsigned)lds0);
+            e = batched ? launch_sigma0_t<T, 2, true>(single, jobs_dev, n_jobs, sp, lds0, stream)
+                        : launch_sigma0_t<T, 2, false>(single, jobs_dev, n_jobs, sp, lds0, stream);
             break;
         case 3:
-            hipLaunchKernelGGL((k_sigma0<T, 3>), dim3(n0), dim3(kBlock), lds0, stream, single,
-                               jobs_dev, n_jobs, sp, (unsigned)lds0);
+            e = batched ? launch_sigma0_t<T, 3, true>(single, jobs_dev, n_jobs, sp, lds0, stream)
+                        : launch_sigma0_t<T, 3, false>(single, jobs_dev, n_jobs, sp, lds0, stream);
             break;
         default:
-            hipLaunchKernelGGL((k_sigma0<T, 4>), dim3(n0), dim3(kBlock), lds0, stream, single,
-                               jobs_dev, n_jobs, sp, (unsigned)lds0);
+            e = batched ? launch_sigma0_t<T, 4, true>(single, jobs_dev, n_jobs, sp, lds0, stream)
+                        : launch_sigma0_t<T, 4, false>(single, jobs_dev, n_jobs, sp, lds0, stream);
             break;
     }
-    hipError_t e = hipGetLastError();
     if (e != hipSuccess || total_tiles == 0) return e;
+    if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
     // MFMA path for 16 <= N (real H); FP64 above N = 48 would need more than
     // 160 KiB of LDS and stays on the FMA path.
     const int nb = bulk_mfma_blocks(N, single.t.h_complex != 0, sizeof(T) == 8 ? 0 : 1);
     if (nb > 0) {
-        const bool herm = single.herm != 0;
-        if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
-        e = launch_mfma<T>(nb, herm, single, jobs_dev, n_jobs, total_tiles, sp, stream);
-        if (e != hipSuccess) return e;
-        if (ev_end) e = hipEventRecord(ev_end, stream);
-        return e;
+        e = launch_mfma<T>(nb, single.herm != 0, single, jobs_dev, n_jobs, total_tiles, sp, stream);
+    } else {
+        // LDS for H and the G-ADO tile: 2 n^2 (1 + G(n)) is not monotone in n, so
+        // a batch whose largest matrix is N x N takes the maximum over n <= N.
+        size_t lds_elems = 0;
+        for (int n = 1; n <= N; ++n)
+            lds_elems = std::max(lds_elems, 2 * (size_t)n * n * (1 + bulk_ados_per_tile(n)));
+        const size_t lds = lds_elems * sizeof(T);
+        e = batched ? launch_fma_t<T, true>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream)
+                    : launch_fma_t<T, false>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream);
     }
-    // bulk: in a batched launch `single` carries the largest N of the batch.
-    // LDS for H and the G-ADO tile: 2 n^2 (1 + G(n)) is not monotone in n, so
-    // a batch whose largest matrix is N x N takes the maximum over n <= N.
-    size_t lds_elems = 0;
-    for (int n = 1; n <= N; ++n)
-        lds_elems = std::max(lds_elems, 2 * (size_t)n * n * (1 + bulk_ados_per_tile(n)));
-    const size_t lds = lds_elems * sizeof(T);
-    if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bulk_fma<T>, dim3(total_tiles), dim3(kBlock), lds, stream, single,
-                       jobs_dev, n_jobs, sp);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (e != hipSuccess) return e;
     if (ev_end) e = hipEventRecord(ev_end, stream);
     return e;
 }
