@@ -43,10 +43,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="aggregate48", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="aggregate48", choices=sorted(WORKLOADS) + ["serve"])
     ap.add_argument("--precision", default="fp32_mixed", choices=["fp32_mixed", "fp64"])
     ap.add_argument("--cpu-baseline-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle sample (0 disables it)")
+    ap.add_argument("--serve-requests", type=int, default=128)
+    ap.add_argument("--serve-steps", type=int, default=1000)
+    ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-arena-gb", type=float, default=48.0)
     return ap.parse_args()
 
 
@@ -80,8 +85,115 @@ def cpu_baseline(prob, target_s):
                                              platform.processor() or platform.machine())}
 
 
+def _percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q / 100.0
+    lo = int(k)
+    hi = min(lo + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def _replay(heom, reqs, precision, max_active, arena_bytes, rate, timeout_s=600.0):
+    """Submit requests at their (scaled) Poisson arrival times; returns
+    latencies (s), makespan (s) and ADO-updates done."""
+    srv = heom.Server(arena_bytes, max_active)
+    t0 = time.monotonic()
+    arrival = 0.0
+    tickets = []
+    for r in reqs:
+        if rate is not None:
+            arrival += r["gap"] / rate
+            delay = t0 + arrival - time.monotonic()
+            if delay > 0:
+                time.sleep(delay)
+        tickets.append(srv.submit(r["runs"], precision))
+    lat, work = [], 0
+    t_end = t0
+    for r, t in zip(reqs, tickets):
+        res = srv.wait(t, timeout_s)
+        if res["status"] != 0:
+            raise RuntimeError("request %d failed: %s" % (r["id"], res["status"]))
+        lat.append(res["t_finish"] - res["t_submit"])
+        t_end = max(t_end, res["t_finish"])
+        work += r["n_ado"] * r["runs"][0]["n_steps"] * len(r["runs"])
+        srv.release(t)
+    srv.close()
+    # t_finish is on the library's monotonic clock, like time.monotonic here
+    return lat, max(t_end - t0, 1e-9), work
+
+
+def run_serve(args):
+    """Serving mix: continuous batching (FP32 bulk, FP64 sigma_0 and
+    reductions) against plain FP64 one-solve-at-a-time on the same GPU."""
+    import torch
+
+    import paper_1803_03498_amd as heom
+    torch.cuda.set_device(0)
+    reqs = hi.serving_mix(n_requests=args.serve_requests, seed=512, n_steps=args.serve_steps)
+    for r in reqs:
+        r["n_ado"] = heom.plan(r["runs"][0])["n_ado"]
+    arena = int(args.serve_arena_gb * (1 << 30))
+    # warm-up: kernels compiled/loaded, allocator primed
+    _replay(heom, reqs[:4], heom.FP32_MIXED, 8, arena, None)
+    torch.cuda.synchronize()
+    # 1. closed-loop capacity of the batched server
+    lat_c, span_c, work_c = _replay(heom, reqs, heom.FP32_MIXED, args.serve_slots, arena, None)
+    capacity = len(reqs) / span_c
+    rate = args.serve_load * capacity
+    print("serve: %d requests, capacity %.2f req/s (%.1f s closed loop), replay at %.2f req/s"
+          % (len(reqs), capacity, span_c, rate), file=sys.stderr, flush=True)
+    # 2. the same Poisson trace through the batched server and through FP64 one-at-a-time
+    lat_b, span_b, work_b = _replay(heom, reqs, heom.FP32_MIXED, args.serve_slots, arena, rate)
+    lat_f, span_f, work_f = _replay(heom, reqs, heom.FP64, 1, arena, rate)
+    line = {
+        "metric": METRIC,
+        "value": work_b / span_b,
+        "unit": "ADO-updates/s",
+        "n_gpus": 1,
+        "steps": args.serve_steps,
+        "warmup": 4,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "serving mix: %d requests (seed 512), N in 2..14, D in 2..5, M in 0..1, "
+                        "population or 3-direction absorption, %d RK4 steps of 1 fs, Poisson "
+                        "arrivals at %.2fx the closed-loop capacity" % (
+                            len(reqs), args.serve_steps, args.serve_load),
+            "slots": args.serve_slots, "arena_GB": args.serve_arena_gb,
+        },
+        "serve": {
+            "capacity_req_per_s": capacity,
+            "arrival_rate_req_per_s": rate,
+            "batched_fp32": {"p50_ms": 1e3 * _percentile(lat_b, 50),
+                             "p99_ms": 1e3 * _percentile(lat_b, 99),
+                             "throughput_req_per_s": len(reqs) / span_b,
+                             "ado_updates_per_s": work_b / span_b},
+            "plain_fp64_one_at_a_time": {"p50_ms": 1e3 * _percentile(lat_f, 50),
+                                         "p99_ms": 1e3 * _percentile(lat_f, 99),
+                                         "throughput_req_per_s": len(reqs) / span_f,
+                                         "ado_updates_per_s": work_f / span_f},
+        },
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "serve":
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only (--gpus %d requested)" % args.gpus,
+                  file=sys.stderr)
+            sys.exit(2)
+        run_serve(args)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)

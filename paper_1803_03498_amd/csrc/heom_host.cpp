@@ -69,7 +69,7 @@ struct Derived {
 struct Layout {
     size_t h_re, h_im, mode_site, mode_gamma, mode_c, mode_lamnu, plus_coef, minus_coef,
         delta_state, state_mode_begin, state_modes, binom, consts_end;
-    size_t tuples, level, plus, minus, damping, total;
+    size_t tuples, level, plus, minus, mlist, damping, total;
 };
 
 Layout make_layout(int N, int W, int D, int64_t n_ado) {
@@ -99,6 +99,7 @@ Layout make_layout(int N, int W, int D, int64_t n_ado) {
     L.level = take((size_t)n_ado);
     L.plus = take((size_t)n_ado * W * 4);
     L.minus = take((size_t)n_ado * W * 4);
+    L.mlist = take((size_t)n_ado * std::max(D, 1) * 8);
     L.damping = take((size_t)n_ado * 8);
     L.total = o;
     return L;
@@ -420,6 +421,7 @@ heom_status heom_build_hierarchy(const heom_problem* problem, void* tables_dev,
     t.level = reinterpret_cast<uint8_t*>(base + L.level);
     t.plus = reinterpret_cast<int32_t*>(base + L.plus);
     t.minus = reinterpret_cast<int32_t*>(base + L.minus);
+    t.mlist = reinterpret_cast<int32_t*>(base + L.mlist);
     t.damping = reinterpret_cast<double*>(base + L.damping);
 
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -596,7 +598,9 @@ heom_status heom_rhs(const heom_hierarchy* h, heom_state in, heom_state out, int
     sp.hmul = 1.0;
     hipError_t e = heom::launch_stage(j, nullptr, 0, h->t.n_ado > 1 ? j.n_tiles : 0,
                                       h->d.precision, sp, static_cast<hipStream_t>(stream));
-    if (e != hipSuccess) return fail(HEOM_E_DEVICE, "rhs launch: %s", hipGetErrorString(e));
+    if (e != hipSuccess)
+        return fail(HEOM_E_DEVICE, "rhs launch (%s): %s", heom::last_launch_failure(),
+                    hipGetErrorString(e));
     return HEOM_OK;
 }
 
@@ -651,7 +655,9 @@ heom_status heom_propagate(const heom_hierarchy* h, heom_state io, void* work_de
             hipError_t e = heom::launch_stage(j, nullptr, 0, tiles, h->d.precision, sp[k], st,
                                               timed ? ev[2 * (step * 4 + k)] : nullptr,
                                               timed ? ev[2 * (step * 4 + k) + 1] : nullptr);
-            if (e != hipSuccess) return fail(HEOM_E_DEVICE, "stage launch: %s", hipGetErrorString(e));
+            if (e != hipSuccess)
+                return fail(HEOM_E_DEVICE, "stage launch (%s): %s", heom::last_launch_failure(),
+                            hipGetErrorString(e));
         }
     }
     if (n_steps == 0) {

@@ -34,6 +34,8 @@ struct Tables {
     uint8_t* level;               // [n_ado]
     int32_t* plus;                // [n_ado][W], -1 = absent
     int32_t* minus;               // [n_ado][W], -1 = absent
+    int32_t* mlist;               // [n_ado][max(D,1)][2]: active "-" links in mode order,
+                                  // [0] = neighbour (-1 = none), [1] = mode | n_l << 8
     double* damping;              // [n_ado]: sum_l n_l gamma_l
 };
 
@@ -77,6 +79,8 @@ hipError_t launch_stage(const Job& single, const Job* jobs_dev, int n_jobs, int 
                         int precision, const StageSpec& sp, hipStream_t stream,
                         hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
 int bulk_ados_per_tile(int N);
+// Name of the kernel whose launch failed in the last launch_stage call on this thread.
+const char* last_launch_failure();
 // Which bulk kernel a job uses: 0 = FMA path, otherwise 16*nb >= N on the MFMA path.
 int bulk_mfma_blocks(int N, bool h_complex, int precision);
 

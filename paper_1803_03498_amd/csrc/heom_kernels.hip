@@ -30,6 +30,7 @@ __device__ __forceinline__ cpx<T> cconj(cpx<T> a) {
 // (re, im) pairs as clang vector types: one 8- or 16-byte access per element.
 typedef float pair_f __attribute__((ext_vector_type(2)));
 typedef double pair_d __attribute__((ext_vector_type(2)));
+typedef int pair_i __attribute__((ext_vector_type(2)));
 template <typename T>
 struct vec2;
 template <>
@@ -133,6 +134,32 @@ __global__ __launch_bounds__(256) void k_links(Tables t) {
     G(t.minus)[idx] = (n[l] > 0) ? (int32_t)rank_with(n, W, G(t.binom), l, -1) : -1;
 }
 
+// Compact list of the active "-" links of every ADO (n_l > 0; at most D of
+// them since |n| <= D), in mode order, padded with -1.  The stage kernels read
+// one row of it instead of walking the tuple.
+__global__ __launch_bounds__(256) void k_minus_list(Tables t) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= t.n_ado) return;
+    const int W = t.W, Dm = t.D > 0 ? t.D : 1;
+    gptr<pair_i> out = G(reinterpret_cast<pair_i*>(t.mlist)) + (size_t)u * Dm;
+    int k = 0;
+    for (int l = 0; l < W && k < Dm; ++l) {
+        const int nl = G(t.tuples)[(size_t)u * W + l];
+        if (nl > 0) {
+            pair_i v;
+            v.x = G(t.minus)[(size_t)u * W + l];
+            v.y = l | (nl << 8);
+            out[k++] = v;
+        }
+    }
+    for (; k < Dm; ++k) {
+        pair_i v;
+        v.x = -1;
+        v.y = 0;
+        out[k] = v;
+    }
+}
+
 // --------------------------------------------------------------------------
 // Right-hand side of eq. HEOM for one matrix element (i, j) of ADO u.
 // Commutator operands come from LDS (sH: H, sS: sigma_u, both interleaved
@@ -159,66 +186,6 @@ __device__ __forceinline__ cpx<T> load_nb(const NbSrc<T>& s, int nb, int r, int 
         return {(T)v.re, (T)v.im};
     }
     return ld<T>(s.rest, (size_t)(nb - 1) * s.N * s.N + (size_t)r * s.N + c);
-}
-
-template <typename T>
-__device__ __forceinline__ cpx<T> rhs_element(const Tables& t, const T* sH, const T* sS, int u,
-                                              int i, int j, bool herm, const NbSrc<T>& nbs) {
-    const int N = t.N, W = t.W, D = t.D;
-    // -i [H, sigma]
-    T cr = 0, ci = 0;
-    for (int k = 0; k < N; ++k) {
-        const T hr = sH[2 * (i * N + k)], hi = sH[2 * (i * N + k) + 1];
-        const T sr = sS[2 * (k * N + j)], si = sS[2 * (k * N + j) + 1];
-        const T tr = sS[2 * (i * N + k)], ti = sS[2 * (i * N + k) + 1];
-        const T gr = sH[2 * (k * N + j)], gi = sH[2 * (k * N + j) + 1];
-        cr += hr * sr - hi * si - (tr * gr - ti * gi);
-        ci += hr * si + hi * sr - (tr * gi + ti * gr);
-    }
-    const T s_r = sS[2 * (i * N + j)], s_i = sS[2 * (i * N + j) + 1];
-    T ar = ci, ai = -cr;  // -i * comm
-    // second line: damping
-    const T gam = (T)G(t.damping)[u];
-    ar -= gam * s_r;
-    ai -= gam * s_i;
-    // third line: correction term, (1 - d_ij)(Delta_i + Delta_j)
-    if (i != j) {
-        const T dl = (T)(G(t.delta_state)[i] + G(t.delta_state)[j]);
-        ar -= dl * s_r;
-        ai -= dl * s_i;
-    }
-    const int lev = (u == 0) ? 0 : G(t.level)[u];
-    gcptr<uint8_t> nu_ = G(t.tuples) + (size_t)u * W;
-    const int npass = (i == j) ? 1 : 2;
-    for (int pass = 0; pass < npass; ++pass) {
-        const int s = pass == 0 ? i : j;
-        const T vx = (T)((i == s) - (j == s));
-        const T vo = (T)((i == s) + (j == s));
-        const bool col = (j == s) && (i != s);
-        for (int m = G(t.state_mode_begin)[s]; m < G(t.state_mode_begin)[s + 1]; ++m) {
-            const int l = G(t.state_modes)[m];
-            const int nl = nu_[l];
-            if (lev < D && i != j) {
-                const int nb = G(t.plus)[(size_t)u * W + l];
-                const cpx<T> x = (herm && col) ? cconj(load_nb<T>(nbs, nb, j, i))
-                                               : load_nb<T>(nbs, nb, i, j);
-                const T a = (T)G(t.plus_coef)[l * (D + 1) + nl] * vx;
-                ar -= a * x.im;  // i * a * x
-                ai += a * x.re;
-            }
-            if (nl > 0) {
-                const int nb = G(t.minus)[(size_t)u * W + l];
-                const cpx<T> x = (herm && col) ? cconj(load_nb<T>(nbs, nb, j, i))
-                                               : load_nb<T>(nbs, nb, i, j);
-                const T b = (T)G(t.minus_coef)[l * (D + 1) + nl];
-                const T thr = b * (T)G(t.mode_lamnu)[l] * vo;  // real part of b*theta
-                const T thi = b * (T)G(t.mode_c)[l] * vx;      // imaginary part
-                ar += thr * x.re - thi * x.im;
-                ai += thr * x.im + thi * x.re;
-            }
-        }
-    }
-    return {ar, ai};
 }
 
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
@@ -332,10 +299,9 @@ __host__ __device__ inline Sigma0Lds sigma0_lds(int N, int W, int tsize, bool he
     return L;
 }
 
-template <typename T, int NB, bool BATCHED>
+template <typename T, bool BATCHED>
 __global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int n_jobs,
                                                 StageSpec sp, unsigned lds_cap) {
-    constexpr int EPT = (16 * NB * 16 * NB + kBlock - 1) / kBlock;
     const Job& J = BATCHED ? jobs[blockIdx.x] : single;
     const Tables& t = J.t;
     const int N = t.N, NN = N * N, W = t.W, D = t.D;
@@ -387,13 +353,8 @@ __global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int
     __syncthreads();
     if (sp.record_initial && tid == 0 && *G(J.step) == 0) record_sigma0(J, sS, 0);
 
-    double nr[EPT], ni[EPT];
     const double h = sp.hmul * J.dt;
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-        const int e = tid + q * kBlock;
-        nr[q] = ni[q] = 0.0;
-        if (e >= NN) continue;
+    for (int e = tid; e < NN; e += blockDim.x) {
         const int i = e / N, j = e - (e / N) * N;
         // -i [H, sigma_0] (the damping vanishes at u = 0)
         double cr = 0, ci = 0;
@@ -440,26 +401,25 @@ __global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int
                 }
             }
         }
-        // RK4 stage combination in FP64
+        // RK4 stage combination in FP64; out may be a base (stage 4), which
+        // only this thread reads at element e.
         double yr = sp.w_in * sS[2 * e], yi = sp.w_in * sS[2 * e + 1];
         for (int m = 0; m < sp.nbase; ++m) {
             const cpx<double> bv = ld<double>(J.sig0[sp.base[m]], e);
             yr += sp.wbase[m] * bv.re;
             yi += sp.wbase[m] * bv.im;
         }
-        nr[q] = yr + h * fr;
-        ni[q] = yi + h * fi;
-    }
-    __syncthreads();  // every thread has read the old sigma_0 from LDS
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-        const int e = tid + q * kBlock;
-        if (e >= NN) continue;
-        st<double>(J.sig0[sp.out], e, cpx<double>{nr[q], ni[q]});
-        sS[2 * e] = nr[q];
-        sS[2 * e + 1] = ni[q];
+        st<double>(J.sig0[sp.out], e, cpx<double>{yr + h * fr, yi + h * fi});
     }
     if (sp.record_after) {
+        // the new sigma_0 back into LDS for the observables
+        __threadfence();
+        __syncthreads();
+        for (int e = tid; e < NN; e += blockDim.x) {
+            const cpx<double> v = ld<double>(J.sig0[sp.out], e);
+            sS[2 * e] = v.re;
+            sS[2 * e + 1] = v.im;
+        }
         __syncthreads();
         if (tid == 0) {
             const int64_t step = *G(J.step) + 1;
@@ -470,51 +430,170 @@ __global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int
 }
 
 // --------------------------------------------------------------------------
-// Bulk stage kernel, wavefront-FMA path: a workgroup takes G consecutive ADOs
-// (G = max(1, 256 / N^2)); every thread owns whole matrix elements.
+// Bulk stage kernel, wavefront-FMA path (N < 16, or complex H): a workgroup
+// takes GA = max(1, 256 / N^2) consecutive ADOs; every thread owns whole
+// matrix elements.  Each ADO's links are staged in LDS first (the compact
+// "-" list, and the "+" row when its level is below D), so an element's
+// coupling lines need one global load per contributing neighbour.
 // --------------------------------------------------------------------------
+struct FmaLds {
+    size_t h, s, mw, pw, mi, pi, lev, st, total;
+};
+
+__host__ __device__ inline FmaLds fma_lds(int N, int W, int D, int GA, int tsize) {
+    const int Dm = D > 0 ? D : 1;
+    const size_t NN = (size_t)N * N;
+    FmaLds L{};
+    size_t o = 0;
+    L.h = o; o += 2 * NN * tsize;
+    L.s = o; o += 2 * NN * (size_t)GA * tsize;
+    L.mw = o; o += 2 * (size_t)GA * Dm * tsize;   // "-" weights (lambda nu, c)
+    L.pw = o; o += (size_t)GA * W * tsize + (size_t)(GA + N) * tsize;  // "+" weights, damping, delta
+    L.mi = o; o += 2 * (size_t)GA * Dm * 4;        // "-" neighbour and state
+    L.pi = o; o += (size_t)GA * W * 4;             // "+" neighbour
+    L.lev = o; o += (size_t)GA * 4;
+    L.st = o; o += (size_t)(N + 1 + W) * 4;        // per-state mode lists
+    L.total = o;
+    return L;
+}
+
 template <typename T, bool BATCHED>
 __global__ __launch_bounds__(256) void k_bulk_fma(Job single, const Job* jobs, int n_jobs,
                                                   StageSpec sp) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const Job& J = JobOf<BATCHED>::get(single, jobs, n_jobs, b);
     const Tables& t = J.t;
-    const int N = t.N, NN = N * N, GA = J.ados_per_tile;
+    const int N = t.N, NN = N * N, W = t.W, D = t.D, Dm = D > 0 ? D : 1;
+    const int GA = J.ados_per_tile;
     const int u0 = 1 + (b - J.tile_begin) * GA;
     const int n_here = min(GA, t.n_ado - u0);
+    const FmaLds L = fma_lds(N, W, D, GA, (int)sizeof(T));
     extern __shared__ char smem_raw[];
-    T* sH = reinterpret_cast<T*>(smem_raw);  // 2*NN
-    T* sS = sH + 2 * NN;                      // 2*GA*NN
+    T* sH = reinterpret_cast<T*>(smem_raw + L.h);     // 2*NN
+    T* sS = reinterpret_cast<T*>(smem_raw + L.s);     // 2*GA*NN
+    T* sMml = reinterpret_cast<T*>(smem_raw + L.mw);  // [GA][Dm]
+    T* sMmc = sMml + GA * Dm;
+    T* sPa = reinterpret_cast<T*>(smem_raw + L.pw);   // [GA][W]
+    T* sGam = sPa + GA * W;                           // [GA]
+    T* sDelta = sGam + GA;                            // [N]
+    int* sMnb = reinterpret_cast<int*>(smem_raw + L.mi);  // [GA][Dm]
+    int* sMsite = sMnb + GA * Dm;
+    int* sPnb = reinterpret_cast<int*>(smem_raw + L.pi);  // [GA][W]
+    int* sLev = reinterpret_cast<int*>(smem_raw + L.lev);
+    int* sBegin = reinterpret_cast<int*>(smem_raw + L.st);  // [N+1]
+    int* sModes = sBegin + N + 1;                            // [W]
     const int tid = threadIdx.x;
+
+    // stage H, the tile, the per-ADO link data and the per-state tables
     for (int e = tid; e < NN; e += blockDim.x) {
         sH[2 * e] = (T)G(t.h_re)[e];
         sH[2 * e + 1] = t.h_complex ? (T)G(t.h_im)[e] : (T)0;
     }
     const size_t base = (size_t)(u0 - 1) * NN;
     const int tot = n_here * NN;
-    const void* in = J.rest[sp.in];
-    for (int e = tid; e < tot; e += blockDim.x) {
-        const cpx<T> v = ld<T>(in, base + e);
-        sS[2 * e] = v.re;
-        sS[2 * e + 1] = v.im;
+    {
+        const void* in = J.rest[sp.in];
+        for (int e = tid; e < tot; e += blockDim.x) {
+            const cpx<T> v = ld<T>(in, base + e);
+            sS[2 * e] = v.re;
+            sS[2 * e + 1] = v.im;
+        }
     }
+    for (int x = tid; x < n_here * Dm; x += blockDim.x) {
+        const int g = x / Dm, a = x - g * Dm;
+        const pair_i ml = G(reinterpret_cast<const pair_i*>(t.mlist))[(size_t)(u0 + g) * Dm + a];
+        sMnb[x] = ml.x;
+        if (ml.x >= 0) {
+            const int mode = ml.y & 255, nl = ml.y >> 8;
+            const double coef = G(t.minus_coef)[mode * (D + 1) + nl];
+            sMsite[x] = G(t.mode_site)[mode];
+            sMml[x] = (T)(coef * G(t.mode_lamnu)[mode]);
+            sMmc[x] = (T)(coef * G(t.mode_c)[mode]);
+        } else {
+            sMsite[x] = -1;
+        }
+    }
+    for (int g = tid; g < n_here; g += blockDim.x) {
+        sLev[g] = G(t.level)[u0 + g];
+        sGam[g] = (T)G(t.damping)[u0 + g];
+    }
+    for (int x = tid; x < n_here * W; x += blockDim.x) {
+        const int g = x / W, l = x - g * W;
+        const int u = u0 + g;
+        if (G(t.level)[u] < D) {
+            const int nl = G(t.tuples)[(size_t)u * W + l];
+            sPnb[x] = G(t.plus)[(size_t)u * W + l];
+            sPa[x] = (T)G(t.plus_coef)[l * (D + 1) + nl];
+        }
+    }
+    for (int x = tid; x <= N; x += blockDim.x) {
+        sBegin[x] = G(t.state_mode_begin)[x];
+        if (x < N) sDelta[x] = (T)G(t.delta_state)[x];
+    }
+    for (int l = tid; l < W; l += blockDim.x) sModes[l] = G(t.state_modes)[l];
     __syncthreads();
+
     const NbSrc<T> nbs{J.sig0[sp.in], J.rest[sp.in], N};
-    const T h = (T)(sp.hmul * J.dt);
-    const T w_in = (T)sp.w_in;
+    const bool herm = J.herm != 0, hc = t.h_complex != 0;
+    const T h = (T)(sp.hmul * J.dt), w_in = (T)sp.w_in;
     for (int e = tid; e < tot; e += blockDim.x) {
         const int g = e / NN;
         const int ij = e - g * NN;
         const int i = ij / N, j = ij - (ij / N) * N;
-        const cpx<T> f = rhs_element<T>(t, sH, sS + 2 * g * NN, u0 + g, i, j, J.herm != 0, nbs);
-        T yr = w_in * sS[2 * e], yi = w_in * sS[2 * e + 1];
+        const T* S = sS + 2 * g * NN;
+        // -i [H, sigma]
+        T cr = 0, ci = 0;
+        if (hc) {
+            for (int k = 0; k < N; ++k) {
+                const T hr = sH[2 * (i * N + k)], hi = sH[2 * (i * N + k) + 1];
+                const T xr = S[2 * (k * N + j)], xi = S[2 * (k * N + j) + 1];
+                const T yr = S[2 * (i * N + k)], yi = S[2 * (i * N + k) + 1];
+                const T gr = sH[2 * (k * N + j)], gi = sH[2 * (k * N + j) + 1];
+                cr += hr * xr - hi * xi - (yr * gr - yi * gi);
+                ci += hr * xi + hi * xr - (yr * gi + yi * gr);
+            }
+        } else {
+            for (int k = 0; k < N; ++k) {
+                const T hik = sH[2 * (i * N + k)], hkj = sH[2 * (k * N + j)];
+                cr += hik * S[2 * (k * N + j)] - S[2 * (i * N + k)] * hkj;
+                ci += hik * S[2 * (k * N + j) + 1] - S[2 * (i * N + k) + 1] * hkj;
+            }
+        }
+        const T sr = S[2 * ij], si = S[2 * ij + 1];
+        const T gm = sGam[g] + ((i != j) ? sDelta[i] + sDelta[j] : (T)0);
+        T fr = ci - gm * sr, fi = -cr - gm * si;
+        for (int a = 0; a < Dm; ++a) {
+            const int s = sMsite[g * Dm + a];
+            if (s < 0 || (i != s && j != s)) continue;
+            const int nb = sMnb[g * Dm + a];
+            const bool col = (j == s) && (i != s);
+            const cpx<T> x = (herm && col) ? cconj(load_nb<T>(nbs, nb, s, i))
+                                           : load_nb<T>(nbs, nb, i, j);
+            const T vx = (T)((i == s) - (j == s)), vo = (T)((i == s) + (j == s));
+            const T thr = sMml[g * Dm + a] * vo, thi = sMmc[g * Dm + a] * vx;
+            fr += thr * x.re - thi * x.im;
+            fi += thr * x.im + thi * x.re;
+        }
+        if (sLev[g] < D && i != j) {
+            for (int pass = 0; pass < 2; ++pass) {
+                const int s = pass == 0 ? i : j;
+                for (int m = sBegin[s]; m < sBegin[s + 1]; ++m) {
+                    const int l = sModes[m];
+                    const int nb = sPnb[g * W + l];
+                    const cpx<T> x = (herm && pass == 1) ? cconj(load_nb<T>(nbs, nb, s, i))
+                                                         : load_nb<T>(nbs, nb, i, j);
+                    const T pa = pass == 0 ? sPa[g * W + l] : -sPa[g * W + l];
+                    fr -= pa * x.im;
+                    fi += pa * x.re;
+                }
+            }
+        }
+        T yr = w_in * sr + h * fr, yi = w_in * si + h * fi;
         for (int m = 0; m < sp.nbase; ++m) {
             const cpx<T> bv = ld<T>(J.rest[sp.base[m]], base + e);
             yr += (T)sp.wbase[m] * bv.re;
             yi += (T)sp.wbase[m] * bv.im;
         }
-        yr += h * f.re;
-        yi += h * f.im;
         st<T>(J.rest[sp.out], base + e, cpx<T>{yr, yi});
     }
 }
@@ -567,98 +646,45 @@ __device__ __forceinline__ int mfma_row<double>(int lane, int r) {
     return 4 * r + (lane >> 4);
 }
 
-// Per-block LDS copies of the small per-problem tables, and the per-ADO link
-// description: every mode's "+" neighbour and coefficient, and a compact list
-// of the active "-" links (modes with n_l > 0, at most D of them) in mode
-// order, built with a wave ballot so that the order is deterministic.
-template <typename T>
-struct BlockTables {
-    int32_t* site;   // [W] mode -> coupled state
-    T* delta;        // [N] correction coefficient per state
-    int32_t* pnb;    // [W] "+" neighbour (valid when level < D)
-    T* pa;           // [W] sign * sqrt((n_l+1)|c_l|)
-    int32_t* msite;  // [W] active "-" links: state, neighbour, coefficients
-    int32_t* mnb;
-    T* mml;          // sqrt(n_l/|c_l|) * sign * lambda nu (k = 0)
-    T* mmc;          // sqrt(n_l/|c_l|) * sign * c_l
-    int32_t* count;  // [4] per-wave active counts, [4] = total
-};
-
-template <typename T>
-__device__ __forceinline__ size_t block_tables_bytes(int N, int W) {
-    return (size_t)W * (4 * sizeof(int32_t) + 3 * sizeof(T)) + (size_t)N * sizeof(T) + 8 * 4;
-}
-
-template <typename T>
-__device__ __forceinline__ BlockTables<T> carve_tables(char* p, int N, int W) {
-    BlockTables<T> b;
-    b.pa = reinterpret_cast<T*>(p);
-    b.mml = b.pa + W;
-    b.mmc = b.mml + W;
-    b.delta = b.mmc + W;
-    b.site = reinterpret_cast<int32_t*>(b.delta + N);
-    b.pnb = b.site + W;
-    b.msite = b.pnb + W;
-    b.mnb = b.msite + W;
-    b.count = b.mnb + W;
-    return b;
-}
-
-// Fill the block tables for ADO u (all threads of the block take part;
-// W <= 255 so one pass of 256 threads covers every mode).  Ends with a barrier.
-template <typename T>
-__device__ void fill_block_tables(const Tables& t, int u, int lev, const BlockTables<T>& b) {
-    const int W = t.W, D = t.D, N = t.N;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int s = tid; s < N; s += blockDim.x) b.delta[s] = (T)G(t.delta_state)[s];
-    const int l = tid;
-    int nl = 0;
-    if (l < W) {
-        nl = G(t.tuples)[(size_t)u * W + l];
-        b.site[l] = G(t.mode_site)[l];
-        b.pnb[l] = (lev < D) ? G(t.plus)[(size_t)u * W + l] : -1;
-        b.pa[l] = (T)G(t.plus_coef)[l * (D + 1) + nl];
-    }
-    const bool act = (l < W) && nl > 0;
-    const unsigned long long mask = __ballot(act);
-    if (lane == 0) b.count[wave] = __popcll(mask);
-    __syncthreads();
-    if (act) {
-        int slot = __popcll(mask & ((1ull << lane) - 1));
-        for (int w = 0; w < wave; ++w) slot += b.count[w];
-        const double coef = G(t.minus_coef)[l * (D + 1) + nl];
-        b.msite[slot] = G(t.mode_site)[l];
-        b.mnb[slot] = G(t.minus)[(size_t)u * W + l];
-        b.mml[slot] = (T)(coef * G(t.mode_lamnu)[l]);
-        b.mmc[slot] = (T)(coef * G(t.mode_c)[l]);
-    }
-    if (tid == 0) b.count[4] = b.count[0] + b.count[1] + b.count[2] + b.count[3];
-    __syncthreads();
-}
-
 // At most this many "-" neighbour rows are prefetched into LDS per ADO
-// (one element per thread for N <= 64); further links read global memory.
+// (one element per thread); further links read global memory directly.
 constexpr int kPrefRows = 4;
 
+// LDS carve-up of the MFMA stage kernel (bytes; T-typed arrays first).
+template <typename T, int NB, bool HERM>
+struct MfmaLds {
+    static constexpr int NP = 16 * NB;
+    static constexpr int LS = NP + 1;  // odd row stride: transposed reads hit distinct banks
+    static constexpr int PLANE = NP * LS;
+    static constexpr int NPLANES = HERM ? 4 : 6;
+    __host__ __device__ static size_t bytes(int N, int W, int D) {
+        const int Dm = D > 0 ? D : 1;
+        return sizeof(T) * ((size_t)PLANE * NPLANES + 2 * kPrefRows * NP + 2 * (size_t)Dm + N +
+                            W) +
+               4 * (2 * (size_t)Dm + W);
+    }
+};
+
 template <typename T, int NB, bool HERM, bool BATCHED>
-__global__ __launch_bounds__(256) void k_bulk_mfma(Job single, const Job* jobs, int n_jobs,
-                                                   StageSpec sp) {
-    constexpr int NP = 16 * NB;                           // padded matrix dimension
-    constexpr int LS = NP + 1;                            // LDS row stride (odd: no conflicts
-                                                          // on the transposed reads of X)
-    constexpr int KS = 4 * NB;                            // k-steps of 4 (K = NP)
-    constexpr int NTC = 2 * NB;                           // column tiles of [Re | Im]
-    constexpr int PLANE = NP * LS;
-    constexpr int EPT = (NP * NP + kBlock - 1) / kBlock;  // elements per thread (upper bound)
+__global__ __launch_bounds__(128 * NB) void k_bulk_mfma(Job single, const Job* jobs, int n_jobs,
+                                                        StageSpec sp) {
+    // Two wavefronts per 16-row block of H: wave (mt, half) computes rows
+    // 16 mt .. 16 mt + 15 of X = H Re(sigma) (half 0) or H Im(sigma) (half 1).
+    constexpr int NT = 128 * NB;
+    using L = MfmaLds<T, NB, HERM>;
+    constexpr int NP = L::NP, LS = L::LS, PLANE = L::PLANE;
+    constexpr int KS = 4 * NB;                        // k-steps of 4
+    constexpr int EPT = (NP * NP + NT - 1) / NT;      // elements per thread (2 NB)
     using acc_t = typename mfma_acc<T>::type;
 
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const Job& J = JobOf<BATCHED>::get(single, jobs, n_jobs, b);
     const Tables& t = J.t;
-    const int N = t.N, NN = N * N, W = t.W, D = t.D;
+    const int N = t.N, NN = N * N, W = t.W, D = t.D, Dm = D > 0 ? D : 1;
     const int u = 1 + (b - J.tile_begin);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
+    const int mt = wave >> 1, half = wave & 1;
 
     extern __shared__ char smem_raw[];
     T* sSre = reinterpret_cast<T*>(smem_raw);
@@ -667,32 +693,52 @@ __global__ __launch_bounds__(256) void k_bulk_mfma(Job single, const Job* jobs, 
     T* sXim = sXre + PLANE;
     T* sYre = sXim + PLANE;  // general path only
     T* sYim = sYre + PLANE;
-    T* sRow = HERM ? sYre : sYim + PLANE;  // kPrefRows x NP complex (Hermitian path)
-    const BlockTables<T> bt = carve_tables<T>(
-        reinterpret_cast<char*>(HERM ? sRow + 2 * kPrefRows * NP : sRow), N, W);
+    T* sRow = sSre + (size_t)PLANE * L::NPLANES;  // kPrefRows x NP complex
+    T* sMml = sRow + 2 * kPrefRows * NP;          // [Dm] lambda nu weight of "-" link a
+    T* sMmc = sMml + Dm;                          // [Dm] c weight
+    T* sDelta = sMmc + Dm;                        // [N]
+    T* sPa = sDelta + N;                          // [W] "+" weights (level < D only)
+    int* sMsite = reinterpret_cast<int*>(sPa + W);  // [Dm]
+    int* sMnb = sMsite + Dm;                        // [Dm]
+    int* sPnb = sMnb + Dm;                          // [W]
 
-    // Own tile: global -> LDS planes (loads first, then the LDS writes).
+    // 1. Independent loads first: link list, own tile, H block of this wave.
+    const int lev = G(t.level)[u];
+    const T gam = (T)G(t.damping)[u];
+    pair_i ml;
+    ml.x = -1;
+    ml.y = 0;
+    if (tid < Dm) ml = G(reinterpret_cast<const pair_i*>(t.mlist))[(size_t)u * Dm + tid];
     const size_t base = (size_t)(u - 1) * NN;
+    cpx<T> own[EPT];
     {
         const void* in = J.rest[sp.in];
-        cpx<T> v[EPT];
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
-            const int e = tid + q * kBlock;
-            v[q] = (e < NN) ? ld<T>(in, base + e) : cpx<T>{(T)0, (T)0};
+            const int e = tid + q * NT;
+            own[q] = (e < NN) ? ld<T>(in, base + e) : cpx<T>{(T)0, (T)0};
         }
+    }
+    T hreg[KS];  // A operand: H[16 mt + lane%16][4 ks + lane/16]
 #pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-            const int e = tid + q * kBlock;
-            if (e < NN) {
-                const int i = e / N, j = e - (e / N) * N;
-                sSre[i * LS + j] = v[q].re;
-                sSim[i * LS + j] = v[q].im;
-            }
+    for (int ks = 0; ks < KS; ++ks) {
+        const int r = 16 * mt + (lane & 15), c = 4 * ks + (lane >> 4);
+        hreg[ks] = (r < N && c < N) ? (T)G(t.h_re)[r * N + c] : (T)0;
+    }
+
+    // 2. LDS: own tile planes, link weights, per-state correction, "+" links.
+    const float invN = 1.0f / (float)N;  // exact row index for e < 4096 (N <= 64)
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int e = tid + q * NT;
+        if (e < NN) {
+            const int i = (int)(((float)e + 0.5f) * invN), j = e - i * N;
+            sSre[i * LS + j] = own[q].re;
+            sSim[i * LS + j] = own[q].im;
         }
     }
     if (N < NP) {
-        for (int idx = tid; idx < NP * NP; idx += kBlock) {
+        for (int idx = tid; idx < NP * NP; idx += NT) {
             const int r = idx / NP, c = idx - (idx / NP) * NP;
             if (r >= N || c >= N) {
                 sSre[r * LS + c] = (T)0;
@@ -700,75 +746,92 @@ __global__ __launch_bounds__(256) void k_bulk_mfma(Job single, const Job* jobs, 
             }
         }
     }
-    const int lev = G(t.level)[u];
-    const T gam = (T)G(t.damping)[u];
-    fill_block_tables<T>(t, u, lev, bt);  // ends with a barrier (also publishes the planes)
+    if (tid < Dm) {
+        const int nb = ml.x, mode = ml.y & 255, nl = ml.y >> 8;
+        sMnb[tid] = nb;
+        if (nb >= 0) {
+            const double coef = G(t.minus_coef)[mode * (D + 1) + nl];
+            sMsite[tid] = G(t.mode_site)[mode];
+            sMml[tid] = (T)(coef * G(t.mode_lamnu)[mode]);
+            sMmc[tid] = (T)(coef * G(t.mode_c)[mode]);
+        } else {
+            sMsite[tid] = -1;
+        }
+    }
+    for (int x = tid; x < N; x += NT) sDelta[x] = (T)G(t.delta_state)[x];
+    if (lev < D) {
+        for (int l = tid; l < W; l += NT) {
+            const int nl = G(t.tuples)[(size_t)u * W + l];
+            sPnb[l] = G(t.plus)[(size_t)u * W + l];
+            sPa[l] = (T)G(t.plus_coef)[l * (D + 1) + nl];
+        }
+    }
+    __syncthreads();
 
-    // Prefetch the row s of every active "-" neighbour (Hermitian path): its
-    // latency hides behind the matrix-core phase.
+    // 3. Prefetch the row s of the first "-" neighbours (Hermitian path) and
+    //    the stage bases; both land while the matrix cores run.
     const NbSrc<T> nbs{J.sig0[sp.in], J.rest[sp.in], N};
-    const int n_minus = bt.count[4];
-    const int n_pref = HERM ? min(n_minus, kPrefRows) : 0;
+    const int n_pref = HERM ? min(Dm, kPrefRows) : 0;
     cpx<T> pre = {(T)0, (T)0};
-    const bool has_pre = tid < n_pref * N;
+    const bool has_pre = tid < n_pref * N && sMnb[tid / N] >= 0;
     if (has_pre) {
         const int a = tid / N, c = tid - (tid / N) * N;
-        pre = load_nb<T>(nbs, bt.mnb[a], bt.msite[a], c);
+        pre = load_nb<T>(nbs, sMnb[a], sMsite[a], c);
     }
-
-    // X = H [Re S | Im S]; H is the A operand, hreg[mt][ks] = H[16 mt + lane%16][4 ks + lane/16]
-    {
-        T hreg[NB][KS];
+    cpx<T> bv[3][EPT];
 #pragma unroll
-        for (int mt = 0; mt < NB; ++mt)
+    for (int m = 0; m < 3; ++m) {
+        if (m < sp.nbase) {
+            const void* bp = J.rest[sp.base[m]];
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const int r = 16 * mt + (lane & 15), c = 4 * ks + (lane >> 4);
-                hreg[mt][ks] = (r < N && c < N) ? (T)G(t.h_re)[r * N + c] : (T)0;
-            }
-        const int ksteps = (N + 3) >> 2;
-#pragma unroll
-        for (int mt = 0; mt < NB; ++mt) {
-            for (int nt = ((wave - mt * NTC) % 4 + 4) % 4; nt < NTC; nt += 4) {
-                const T* plane = nt < NB ? sSre : sSim;
-                const int c0 = 16 * (nt < NB ? nt : nt - NB);
-                acc_t acc = {0, 0, 0, 0};
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks) {
-                    if (ks < ksteps) {
-                        const T bv = plane[(4 * ks + (lane >> 4)) * LS + c0 + (lane & 15)];
-                        acc = mfma16(hreg[mt][ks], bv, acc);
-                    }
-                }
-                T* out = nt < NB ? sXre : sXim;
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    out[(16 * mt + mfma_row<T>(lane, r)) * LS + c0 + (lane & 15)] = acc[r];
+            for (int q = 0; q < EPT; ++q) {
+                const int e = tid + q * NT;
+                bv[m][q] = (e < NN) ? ld<T>(bp, base + e) : cpx<T>{(T)0, (T)0};
             }
         }
-        if (!HERM) {
-            // Y = S H (H real symmetric: the B operand H[k][j] has the A layout)
+    }
+
+    // 4. X = H [Re S | Im S]: this wave's 16-row block against every column block.
+    const int ksteps = (N + 3) >> 2;
+    {
+        const T* plane = half ? sSim : sSre;
+        T* out = half ? sXim : sXre;
 #pragma unroll
-            for (int mt = 0; mt < 2 * NB; ++mt) {
-                const T* plane = mt < NB ? sSre : sSim;
-                const int r0 = 16 * (mt < NB ? mt : mt - NB);
+        for (int cb = 0; cb < NB; ++cb) {
+            acc_t acc = {0, 0, 0, 0};
 #pragma unroll
-                for (int nt = 0; nt < NB; ++nt) {
-                    if (((mt * NB + nt) & 3) != wave) continue;
-                    acc_t acc = {0, 0, 0, 0};
-#pragma unroll
-                    for (int ks = 0; ks < KS; ++ks) {
-                        if (ks < ksteps) {
-                            const T av = plane[(r0 + (lane & 15)) * LS + 4 * ks + (lane >> 4)];
-                            acc = mfma16(av, hreg[nt][ks], acc);
-                        }
-                    }
-                    T* out = mt < NB ? sYre : sYim;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        out[(r0 + mfma_row<T>(lane, r)) * LS + 16 * nt + (lane & 15)] = acc[r];
+            for (int ks = 0; ks < KS; ++ks) {
+                if (ks < ksteps) {
+                    const T bval = plane[(4 * ks + (lane >> 4)) * LS + 16 * cb + (lane & 15)];
+                    acc = mfma16(hreg[ks], bval, acc);
                 }
             }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                out[(16 * mt + mfma_row<T>(lane, r)) * LS + 16 * cb + (lane & 15)] = acc[r];
+        }
+    }
+    if (!HERM) {
+        // Y = S H: wave w takes row block w of [Re S; Im S] (2 NB blocks, one per
+        // wave); H (real symmetric) as the B operand, read per column block.
+        const T* plane = wave < NB ? sSre : sSim;
+        T* out = wave < NB ? sYre : sYim;
+        const int r0 = 16 * (wave < NB ? wave : wave - NB);
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+            acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                if (ks < ksteps) {
+                    const int kr = 4 * ks + (lane >> 4), jc = 16 * cb + (lane & 15);
+                    const T hb = (kr < N && jc < N) ? (T)G(t.h_re)[kr * N + jc] : (T)0;
+                    const T av = plane[(r0 + (lane & 15)) * LS + 4 * ks + (lane >> 4)];
+                    acc = mfma16(av, hb, acc);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                out[(r0 + mfma_row<T>(lane, r)) * LS + 16 * cb + (lane & 15)] = acc[r];
         }
     }
     if (has_pre) {
@@ -777,13 +840,12 @@ __global__ __launch_bounds__(256) void k_bulk_mfma(Job single, const Job* jobs, 
     }
     __syncthreads();
 
-    // Elementwise lines: -i[H, sigma], damping, correction, couplings.  Each
-    // thread reads only its own elements of the sigma planes here, so the
-    // stage value w_in * sigma + h * f goes back into the same slots.
-    const float invN = 1.0f / (float)N;  // exact row index for e < 4096 (N <= 64)
+    // 5. Elementwise lines: -i[H, sigma], damping, correction, couplings.  A
+    //    thread reads only its own elements of the sigma planes here, so the
+    //    value w_in * sigma + h * f goes back into the same slots.
     const T h = (T)(sp.hmul * J.dt), w_in = (T)sp.w_in;
 #pragma unroll 1
-    for (int e = tid; e < NN; e += kBlock) {
+    for (int e = tid; e < NN; e += NT) {
         const int i = (int)(((float)e + 0.5f) * invN), j = e - i * N;
         T cr, ci;
         if (HERM) {
@@ -794,11 +856,11 @@ __global__ __launch_bounds__(256) void k_bulk_mfma(Job single, const Job* jobs, 
             ci = sXim[i * LS + j] - sYim[i * LS + j];
         }
         const T sr = sSre[i * LS + j], si = sSim[i * LS + j];
-        const T g = gam + ((i != j) ? bt.delta[i] + bt.delta[j] : (T)0);
+        const T g = gam + ((i != j) ? sDelta[i] + sDelta[j] : (T)0);
         T fr = ci - g * sr, fi = -cr - g * si;
-        for (int a = 0; a < n_minus; ++a) {
-            const int s = bt.msite[a];
-            if (i != s && j != s) continue;
+        for (int a = 0; a < Dm; ++a) {
+            const int s = sMsite[a];
+            if (s < 0 || (i != s && j != s)) continue;
             const bool col = (j == s) && (i != s);
             cpx<T> x;
             if (a < n_pref) {
@@ -806,11 +868,11 @@ __global__ __launch_bounds__(256) void k_bulk_mfma(Job single, const Job* jobs, 
                 x = {sRow[2 * (a * N + c)], sRow[2 * (a * N + c) + 1]};
                 if (col) x = cconj(x);
             } else {
-                x = (HERM && col) ? cconj(load_nb<T>(nbs, bt.mnb[a], s, i))
-                                  : load_nb<T>(nbs, bt.mnb[a], i, j);
+                x = (HERM && col) ? cconj(load_nb<T>(nbs, sMnb[a], s, i))
+                                  : load_nb<T>(nbs, sMnb[a], i, j);
             }
             const T vx = (T)((i == s) - (j == s)), vo = (T)((i == s) + (j == s));
-            const T thr = bt.mml[a] * vo, thi = bt.mmc[a] * vx;
+            const T thr = sMml[a] * vo, thi = sMmc[a] * vx;
             fr += thr * x.re - thi * x.im;
             fi += thr * x.im + thi * x.re;
         }
@@ -819,10 +881,10 @@ __global__ __launch_bounds__(256) void k_bulk_mfma(Job single, const Job* jobs, 
                 const int s = pass == 0 ? i : j;
                 for (int m = G(t.state_mode_begin)[s]; m < G(t.state_mode_begin)[s + 1]; ++m) {
                     const int l = G(t.state_modes)[m];
-                    const int nb = bt.pnb[l];
+                    const int nb = sPnb[l];
                     const cpx<T> x = (HERM && pass == 1) ? cconj(load_nb<T>(nbs, nb, s, i))
                                                          : load_nb<T>(nbs, nb, i, j);
-                    const T pa = pass == 0 ? bt.pa[l] : -bt.pa[l];  // i * pa * vx * x
+                    const T pa = pass == 0 ? sPa[l] : -sPa[l];  // i * pa * vx * x
                     fr -= pa * x.im;
                     fi += pa * x.re;
                 }
@@ -831,43 +893,27 @@ __global__ __launch_bounds__(256) void k_bulk_mfma(Job single, const Job* jobs, 
         sSre[i * LS + j] = w_in * sr + h * fr;
         sSim[i * LS + j] = w_in * si + h * fi;
     }
-    // RK4 stage combination: per base array, every load first, then the sums.
-    for (int m = 0; m < sp.nbase; ++m) {
-        const T w = (T)sp.wbase[m];
-        const void* bp = J.rest[sp.base[m]];
-        cpx<T> v[EPT];
-#pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-            const int e = tid + q * kBlock;
-            v[q] = (e < NN) ? ld<T>(bp, base + e) : cpx<T>{(T)0, (T)0};
-        }
-#pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-            const int e = tid + q * kBlock;
-            if (e < NN) {
-                const int i = (int)(((float)e + 0.5f) * invN), j = e - i * N;
-                sSre[i * LS + j] += w * v[q].re;
-                sSim[i * LS + j] += w * v[q].im;
-            }
-        }
-    }
+
+    // 6. RK4 stage combination with the prefetched bases, then the stores.
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
-        const int e = tid + q * kBlock;
+        const int e = tid + q * NT;
         if (e < NN) {
             const int i = (int)(((float)e + 0.5f) * invN), j = e - i * N;
-            st<T>(J.rest[sp.out], base + e, cpx<T>{sSre[i * LS + j], sSim[i * LS + j]});
+            T yr = sSre[i * LS + j], yi = sSim[i * LS + j];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                if (m < sp.nbase) {
+                    const T w = (T)sp.wbase[m];
+                    yr += w * bv[m][q].re;
+                    yi += w * bv[m][q].im;
+                }
+            }
+            st<T>(J.rest[sp.out], base + e, cpx<T>{yr, yi});
         }
     }
 }
 
-template <typename T, int NB, bool HERM>
-size_t mfma_lds_bytes(int N, int W) {
-    constexpr int NP = 16 * NB;
-    constexpr int LS = NP + 1;
-    return sizeof(T) * ((size_t)NP * LS * (HERM ? 4 : 6) + (HERM ? 2 * kPrefRows * NP : 0)) +
-           (size_t)W * (4 * 4 + 3 * sizeof(T)) + (size_t)N * sizeof(T) + 8 * 4;
-}
 
 }  // namespace
 
@@ -885,9 +931,13 @@ hipError_t launch_enumerate(const Tables& t, hipStream_t stream) {
     if (t.n_ado <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_enumerate, dim3((t.n_ado + 255) / 256), dim3(256), 0, stream, t);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || t.W == 0) return e;
-    const int64_t n = (int64_t)t.n_ado * t.W;
-    hipLaunchKernelGGL(k_links, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, t);
+    if (e != hipSuccess) return e;
+    if (t.W > 0) {
+        const int64_t n = (int64_t)t.n_ado * t.W;
+        hipLaunchKernelGGL(k_links, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, t);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_minus_list, dim3((t.n_ado + 255) / 256), dim3(256), 0, stream, t);
     return hipGetLastError();
 }
 
@@ -902,9 +952,9 @@ static hipError_t launch_mfma_t(const Job& single, const Job* jobs_dev, int n_jo
         if (a != hipSuccess) return a;
         attr_set = true;
     }
-    const size_t lds = mfma_lds_bytes<T, NB, HERM>(single.t.N, single.t.W);
-    hipLaunchKernelGGL((k_bulk_mfma<T, NB, HERM, BATCHED>), dim3(total_tiles), dim3(kBlock), lds,
-                       stream, single, jobs_dev, n_jobs, sp);
+    const size_t lds = MfmaLds<T, NB, HERM>::bytes(single.t.N, single.t.W, single.t.D);
+    hipLaunchKernelGGL((k_bulk_mfma<T, NB, HERM, BATCHED>), dim3(total_tiles), dim3(128 * NB),
+                       lds, stream, single, jobs_dev, n_jobs, sp);
     return hipGetLastError();
 }
 
@@ -937,17 +987,17 @@ static hipError_t launch_mfma(int nb, bool herm, const Job& single, const Job* j
     }
 }
 
-template <typename T, int NB, bool BATCHED>
+template <typename T, bool BATCHED>
 static hipError_t launch_sigma0_t(const Job& single, const Job* jobs_dev, int n_jobs,
                                   const StageSpec& sp, size_t lds, hipStream_t stream) {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sigma0<T, NB, BATCHED>),
+        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sigma0<T, BATCHED>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (a != hipSuccess) return a;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_sigma0<T, NB, BATCHED>), dim3(BATCHED ? n_jobs : 1), dim3(kBlock), lds,
+    hipLaunchKernelGGL((k_sigma0<T, BATCHED>), dim3(BATCHED ? n_jobs : 1), dim3(kBlock), lds,
                        stream, single, jobs_dev, n_jobs, sp, (unsigned)lds);
     return hipGetLastError();
 }
@@ -968,6 +1018,8 @@ static hipError_t launch_fma_t(const Job& single, const Job* jobs_dev, int n_job
     return hipGetLastError();
 }
 
+thread_local const char* g_launch_what = "";
+
 template <typename T>
 static hipError_t launch_stage_t(const Job& single, const Job* jobs_dev, int n_jobs,
                                  int total_tiles, const StageSpec& sp, hipStream_t stream,
@@ -976,25 +1028,9 @@ static hipError_t launch_stage_t(const Job& single, const Job* jobs_dev, int n_j
     const bool batched = jobs_dev != nullptr;
     // sigma_0: largest N and W of the batch; non-Hermitian staging needs the most LDS
     const size_t lds0 = sigma0_lds(N, single.t.W, (int)sizeof(T), false, 160 * 1024).total;
-    hipError_t e;
-    switch ((N + 15) / 16) {
-        case 1:
-            e = batched ? launch_sigma0_t<T, 1, true>(single, jobs_dev, n_jobs, sp, lds0, stream)
-                        : launch_sigma0_t<T, 1, false>(single, jobs_dev, n_jobs, sp, lds0, stream);
-            break;
-        case 2:
-            e = batched ? launch_sigma0_t<T, 2, true>(single, jobs_dev, n_jobs, sp, lds0, stream)
-                        : launch_sigma0_t<T, 2, false>(single, jobs_dev, n_jobs, sp, lds0, stream);
-            break;
-        case 3:
-            e = batched ? launch_sigma0_t<T, 3, true>(single, jobs_dev, n_jobs, sp, lds0, stream)
-                        : launch_sigma0_t<T, 3, false>(single, jobs_dev, n_jobs, sp, lds0, stream);
-            break;
-        default:
-            e = batched ? launch_sigma0_t<T, 4, true>(single, jobs_dev, n_jobs, sp, lds0, stream)
-                        : launch_sigma0_t<T, 4, false>(single, jobs_dev, n_jobs, sp, lds0, stream);
-            break;
-    }
+    hipError_t e = batched ? launch_sigma0_t<T, true>(single, jobs_dev, n_jobs, sp, lds0, stream)
+                           : launch_sigma0_t<T, false>(single, jobs_dev, n_jobs, sp, lds0, stream);
+    if (e != hipSuccess) g_launch_what = "sigma_0 stage kernel";
     if (e != hipSuccess || total_tiles == 0) return e;
     if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
     // MFMA path for 16 <= N (real H); FP64 above N = 48 would need more than
@@ -1002,24 +1038,29 @@ static hipError_t launch_stage_t(const Job& single, const Job* jobs_dev, int n_j
     const int nb = bulk_mfma_blocks(N, single.t.h_complex != 0, sizeof(T) == 8 ? 0 : 1);
     if (nb > 0) {
         e = launch_mfma<T>(nb, single.herm != 0, single, jobs_dev, n_jobs, total_tiles, sp, stream);
+        if (e != hipSuccess) g_launch_what = "MFMA bulk stage kernel";
     } else {
-        // LDS for H and the G-ADO tile: 2 n^2 (1 + G(n)) is not monotone in n, so
-        // a batch whose largest matrix is N x N takes the maximum over n <= N.
-        size_t lds_elems = 0;
+        // LDS of a tile is not monotone in n (G(n) = 256 / n^2), so a batch
+        // whose largest matrix is N x N takes the maximum over n <= N.
+        size_t lds = 0;
         for (int n = 1; n <= N; ++n)
-            lds_elems = std::max(lds_elems, 2 * (size_t)n * n * (1 + bulk_ados_per_tile(n)));
-        const size_t lds = lds_elems * sizeof(T);
+            lds = std::max(lds, fma_lds(n, single.t.W, single.t.D, bulk_ados_per_tile(n),
+                                        (int)sizeof(T)).total);
         e = batched ? launch_fma_t<T, true>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream)
                     : launch_fma_t<T, false>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream);
+        if (e != hipSuccess) g_launch_what = "FMA bulk stage kernel";
     }
     if (e != hipSuccess) return e;
     if (ev_end) e = hipEventRecord(ev_end, stream);
     return e;
 }
 
+const char* last_launch_failure() { return g_launch_what; }
+
 hipError_t launch_stage(const Job& single, const Job* jobs_dev, int n_jobs, int total_tiles,
                         int precision, const StageSpec& sp, hipStream_t stream,
                         hipEvent_t ev_begin, hipEvent_t ev_end) {
+    g_launch_what = "";
     if (precision == 0)
         return launch_stage_t<double>(single, jobs_dev, n_jobs, total_tiles, sp, stream,
                                       ev_begin, ev_end);

@@ -311,18 +311,21 @@ bool heom_server::rebuild() {
         g.job_off = off;
         g.n_jobs = (int)kv.second.size();
         g.sizing = *kv.second.front();
-        int maxN = 0, maxW = 0, tiles = 0;
+        int maxN = 0, maxW = 0, maxD = 0, tiles = 0;
         for (const heom::Job* j : kv.second) {
             heom::Job c = *j;
             c.tile_begin = tiles;
             tiles += (c.t.n_ado > 1) ? c.n_tiles : 0;
             maxN = std::max(maxN, c.t.N);
             maxW = std::max(maxW, c.t.W);
+            maxD = std::max(maxD, c.t.D);
             jobs_stage[off++] = c;
         }
         g.tiles = tiles;
+        // the launch sizes LDS for the largest N, W and D of the group
         g.sizing.t.N = maxN;
         g.sizing.t.W = maxW;
+        g.sizing.t.D = maxD;
         g.sizing.herm = g.herm;
         if (g.nb == 0) g.sizing.t.h_complex = 1;  // selects the FMA path for any N
         groups.push_back(g);
