@@ -481,7 +481,10 @@ heom::Job base_job(const heom_hierarchy* h) {
     j.t = h->t;
     j.dt = 1.0;
     j.tile_begin = 0;
-    j.ados_per_tile = heom::bulk_ados_per_tile(h->t.N);
+    j.ados_per_tile =
+        heom::bulk_mfma_blocks(h->t.N, h->t.h_complex != 0, h->d.precision)
+            ? 1
+            : heom::bulk_ados_per_tile(h->t.N, h->t.W, h->t.D, h->d.precision == HEOM_FP64 ? 8 : 4);
     j.n_tiles = (int32_t)((h->t.n_ado - 1 + j.ados_per_tile - 1) / j.ados_per_tile);
     j.rec_every = 1;
     return j;

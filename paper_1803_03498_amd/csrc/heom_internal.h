@@ -50,6 +50,7 @@ struct Job {
     int32_t tile_begin;           // first bulk tile of this job in a batched launch
     int32_t n_tiles;              // bulk tiles of this job
     int32_t ados_per_tile;
+    uint32_t lds_bytes;           // batched launches: LDS of the largest tile (0 = derive)
     double* records;              // [n_rec_max][rec_doubles]
     const double* mu;             // [N] (dipole observable)
     int64_t* step;                // device step counter
@@ -78,7 +79,30 @@ hipError_t launch_enumerate(const Tables& t, hipStream_t stream);
 hipError_t launch_stage(const Job& single, const Job* jobs_dev, int n_jobs, int total_tiles,
                         int precision, const StageSpec& sp, hipStream_t stream,
                         hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
-int bulk_ados_per_tile(int N);
+// LDS carve-up of an FMA-path tile of GA ADOs (bytes).
+struct FmaLds {
+    size_t h, s, mw, pw, mi, pi, lev, st, total;
+};
+
+__host__ __device__ inline FmaLds fma_lds(int N, int W, int D, int GA, int tsize) {
+    const int Dm = D > 0 ? D : 1;
+    const size_t NN = (size_t)N * N;
+    FmaLds L{};
+    size_t o = 0;
+    L.h = o; o += 2 * NN * tsize;
+    L.s = o; o += 2 * NN * (size_t)GA * tsize;
+    L.mw = o; o += 2 * (size_t)GA * Dm * tsize;                           // "-" weights
+    L.pw = o; o += (size_t)GA * W * tsize + (size_t)(GA + N) * tsize;      // "+" weights, damping, delta
+    L.mi = o; o += 2 * (size_t)GA * Dm * 4;                                // "-" neighbour and state
+    L.pi = o; o += (size_t)GA * W * 4;                                     // "+" neighbour
+    L.lev = o; o += (size_t)GA * 4;
+    L.st = o; o += (size_t)(N + 1 + W) * 4;                                // per-state mode lists
+    L.total = o;
+    return L;
+}
+
+// ADOs per FMA-path tile: 256 / N^2 threads' worth, reduced to fit 64 KiB of LDS.
+int bulk_ados_per_tile(int N, int W, int D, int tsize);
 // Name of the kernel whose launch failed in the last launch_stage call on this thread.
 const char* last_launch_failure();
 // Which bulk kernel a job uses: 0 = FMA path, otherwise 16*nb >= N on the MFMA path.

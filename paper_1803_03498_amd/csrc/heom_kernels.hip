@@ -436,27 +436,6 @@ __global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int
 // "-" list, and the "+" row when its level is below D), so an element's
 // coupling lines need one global load per contributing neighbour.
 // --------------------------------------------------------------------------
-struct FmaLds {
-    size_t h, s, mw, pw, mi, pi, lev, st, total;
-};
-
-__host__ __device__ inline FmaLds fma_lds(int N, int W, int D, int GA, int tsize) {
-    const int Dm = D > 0 ? D : 1;
-    const size_t NN = (size_t)N * N;
-    FmaLds L{};
-    size_t o = 0;
-    L.h = o; o += 2 * NN * tsize;
-    L.s = o; o += 2 * NN * (size_t)GA * tsize;
-    L.mw = o; o += 2 * (size_t)GA * Dm * tsize;   // "-" weights (lambda nu, c)
-    L.pw = o; o += (size_t)GA * W * tsize + (size_t)(GA + N) * tsize;  // "+" weights, damping, delta
-    L.mi = o; o += 2 * (size_t)GA * Dm * 4;        // "-" neighbour and state
-    L.pi = o; o += (size_t)GA * W * 4;             // "+" neighbour
-    L.lev = o; o += (size_t)GA * 4;
-    L.st = o; o += (size_t)(N + 1 + W) * 4;        // per-state mode lists
-    L.total = o;
-    return L;
-}
-
 template <typename T, bool BATCHED>
 __global__ __launch_bounds__(256) void k_bulk_fma(Job single, const Job* jobs, int n_jobs,
                                                   StageSpec sp) {
@@ -654,25 +633,49 @@ constexpr int kPrefRows = 4;
 template <typename T, int NB, bool HERM>
 struct MfmaLds {
     static constexpr int NP = 16 * NB;
-    static constexpr int LS = NP + 1;  // odd row stride: transposed reads hit distinct banks
+    // sigma (and Y) planes: rows 16 banks apart, so the four rows of an MFMA
+    // B-operand read fall in distinct banks
+    static constexpr int LS = (NP % 32 == 16) ? NP : NP + 16;
+    // X planes: odd stride, so the transposed reads X[j][i] hit distinct banks
+    static constexpr int LX = NP + 1;
     static constexpr int PLANE = NP * LS;
-    static constexpr int NPLANES = HERM ? 4 : 6;
+    static constexpr int XPLANE = NP * LX;
     __host__ __device__ static size_t bytes(int N, int W, int D) {
         const int Dm = D > 0 ? D : 1;
-        return sizeof(T) * ((size_t)PLANE * NPLANES + 2 * kPrefRows * NP + 2 * (size_t)Dm + N +
-                            W) +
+        return sizeof(T) * ((size_t)PLANE * (HERM ? 2 : 4) + 2 * (size_t)XPLANE +
+                            2 * kPrefRows * NP + 2 * (size_t)Dm + N + W) +
                4 * (2 * (size_t)Dm + W);
     }
 };
 
+// Wave-uniform value into a scalar register.
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float uniform(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ double uniform(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Waves per SIMD to ask of the register allocator: four 6-wave workgroups of
+// the FP32 N <= 48 kernel fill a CU's 160 KiB of LDS, which needs <= 80 VGPRs.
+template <typename T, int NB>
+constexpr int mfma_waves_per_eu() {
+    return (sizeof(T) == 4 && NB == 3) ? 6 : 1;
+}
+
 template <typename T, int NB, bool HERM, bool BATCHED>
-__global__ __launch_bounds__(128 * NB) void k_bulk_mfma(Job single, const Job* jobs, int n_jobs,
-                                                        StageSpec sp) {
+__global__ __launch_bounds__(128 * NB) __attribute__((amdgpu_waves_per_eu(
+    mfma_waves_per_eu<T, NB>()))) void k_bulk_mfma(Job single, const Job* jobs, int n_jobs,
+                                                   StageSpec sp) {
     // Two wavefronts per 16-row block of H: wave (mt, half) computes rows
     // 16 mt .. 16 mt + 15 of X = H Re(sigma) (half 0) or H Im(sigma) (half 1).
     constexpr int NT = 128 * NB;
     using L = MfmaLds<T, NB, HERM>;
-    constexpr int NP = L::NP, LS = L::LS, PLANE = L::PLANE;
+    constexpr int NP = L::NP, LS = L::LS, LX = L::LX, PLANE = L::PLANE, XPLANE = L::XPLANE;
     constexpr int KS = 4 * NB;                        // k-steps of 4
     constexpr int EPT = (NP * NP + NT - 1) / NT;      // elements per thread (2 NB)
     using acc_t = typename mfma_acc<T>::type;
@@ -689,11 +692,11 @@ __global__ __launch_bounds__(128 * NB) void k_bulk_mfma(Job single, const Job* j
     extern __shared__ char smem_raw[];
     T* sSre = reinterpret_cast<T*>(smem_raw);
     T* sSim = sSre + PLANE;
-    T* sXre = sSim + PLANE;
-    T* sXim = sXre + PLANE;
-    T* sYre = sXim + PLANE;  // general path only
+    T* sXre = sSim + PLANE;  // stride LX
+    T* sXim = sXre + XPLANE;
+    T* sYre = sXim + XPLANE;  // general path only
     T* sYim = sYre + PLANE;
-    T* sRow = sSre + (size_t)PLANE * L::NPLANES;  // kPrefRows x NP complex
+    T* sRow = HERM ? sYre : sYim + PLANE;  // kPrefRows x NP complex
     T* sMml = sRow + 2 * kPrefRows * NP;          // [Dm] lambda nu weight of "-" link a
     T* sMmc = sMml + Dm;                          // [Dm] c weight
     T* sDelta = sMmc + Dm;                        // [N]
@@ -808,7 +811,7 @@ __global__ __launch_bounds__(128 * NB) void k_bulk_mfma(Job single, const Job* j
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                out[(16 * mt + mfma_row<T>(lane, r)) * LS + 16 * cb + (lane & 15)] = acc[r];
+                out[(16 * mt + mfma_row<T>(lane, r)) * LX + 16 * cb + (lane & 15)] = acc[r];
         }
     }
     if (!HERM) {
@@ -842,35 +845,55 @@ __global__ __launch_bounds__(128 * NB) void k_bulk_mfma(Job single, const Job* j
 
     // 5. Elementwise lines: -i[H, sigma], damping, correction, couplings.  A
     //    thread reads only its own elements of the sigma planes here, so the
-    //    value w_in * sigma + h * f goes back into the same slots.
+    //    value w_in * sigma + h * f goes back into the same slots.  The first
+    //    kPrefRows "-" links are wave-uniform and held in scalar registers.
     const T h = (T)(sp.hmul * J.dt), w_in = (T)sp.w_in;
-#pragma unroll 1
+    int lsite[kPrefRows];
+    T lml[kPrefRows], lmc[kPrefRows];
+#pragma unroll
+    for (int a = 0; a < kPrefRows; ++a) {
+        lsite[a] = uniform(a < Dm ? sMsite[a] : -1);
+        lml[a] = uniform(a < Dm ? sMml[a] : (T)0);
+        lmc[a] = uniform(a < Dm ? sMmc[a] : (T)0);
+    }
+#pragma unroll 2
     for (int e = tid; e < NN; e += NT) {
         const int i = (int)(((float)e + 0.5f) * invN), j = e - i * N;
         T cr, ci;
         if (HERM) {
-            cr = sXre[i * LS + j] - sXre[j * LS + i];
-            ci = sXim[i * LS + j] + sXim[j * LS + i];
+            cr = sXre[i * LX + j] - sXre[j * LX + i];
+            ci = sXim[i * LX + j] + sXim[j * LX + i];
         } else {
-            cr = sXre[i * LS + j] - sYre[i * LS + j];
-            ci = sXim[i * LS + j] - sYim[i * LS + j];
+            cr = sXre[i * LX + j] - sYre[i * LS + j];
+            ci = sXim[i * LX + j] - sYim[i * LS + j];
         }
         const T sr = sSre[i * LS + j], si = sSim[i * LS + j];
         const T g = gam + ((i != j) ? sDelta[i] + sDelta[j] : (T)0);
         T fr = ci - g * sr, fi = -cr - g * si;
-        for (int a = 0; a < Dm; ++a) {
-            const int s = sMsite[a];
+#pragma unroll
+        for (int a = 0; a < kPrefRows; ++a) {
+            const int s = lsite[a];
             if (s < 0 || (i != s && j != s)) continue;
             const bool col = (j == s) && (i != s);
             cpx<T> x;
-            if (a < n_pref) {
+            if (HERM) {
                 const int c = col ? i : j;  // Hermitian: column s is conj(row s)
                 x = {sRow[2 * (a * N + c)], sRow[2 * (a * N + c) + 1]};
                 if (col) x = cconj(x);
             } else {
-                x = (HERM && col) ? cconj(load_nb<T>(nbs, sMnb[a], s, i))
-                                  : load_nb<T>(nbs, sMnb[a], i, j);
+                x = load_nb<T>(nbs, sMnb[a], i, j);
             }
+            const T vx = (T)((i == s) - (j == s)), vo = (T)((i == s) + (j == s));
+            const T thr = lml[a] * vo, thi = lmc[a] * vx;
+            fr += thr * x.re - thi * x.im;
+            fi += thr * x.im + thi * x.re;
+        }
+        for (int a = kPrefRows; a < Dm; ++a) {
+            const int s = sMsite[a];
+            if (s < 0 || (i != s && j != s)) continue;
+            const bool col = (j == s) && (i != s);
+            const cpx<T> x = (HERM && col) ? cconj(load_nb<T>(nbs, sMnb[a], s, i))
+                                           : load_nb<T>(nbs, sMnb[a], i, j);
             const T vx = (T)((i == s) - (j == s)), vo = (T)((i == s) + (j == s));
             const T thr = sMml[a] * vo, thi = sMmc[a] * vx;
             fr += thr * x.re - thi * x.im;
@@ -922,9 +945,12 @@ int bulk_mfma_blocks(int N, bool h_complex, int precision) {
     return (N + 15) / 16;
 }
 
-int bulk_ados_per_tile(int N) {
+int bulk_ados_per_tile(int N, int W, int D, int tsize) {
     const int NN = N * N;
-    return NN >= kBlock ? 1 : kBlock / NN;
+    int g = NN >= kBlock ? 1 : kBlock / NN;
+    // keep a tile's LDS (matrices plus staged links) within 64 KiB
+    while (g > 1 && fma_lds(N, W, D, g, tsize).total > 64 * 1024) --g;
+    return g;
 }
 
 hipError_t launch_enumerate(const Tables& t, hipStream_t stream) {
@@ -1040,12 +1066,11 @@ static hipError_t launch_stage_t(const Job& single, const Job* jobs_dev, int n_j
         e = launch_mfma<T>(nb, single.herm != 0, single, jobs_dev, n_jobs, total_tiles, sp, stream);
         if (e != hipSuccess) g_launch_what = "MFMA bulk stage kernel";
     } else {
-        // LDS of a tile is not monotone in n (G(n) = 256 / n^2), so a batch
-        // whose largest matrix is N x N takes the maximum over n <= N.
-        size_t lds = 0;
-        for (int n = 1; n <= N; ++n)
-            lds = std::max(lds, fma_lds(n, single.t.W, single.t.D, bulk_ados_per_tile(n),
-                                        (int)sizeof(T)).total);
+        // batched launches carry the largest tile LDS of the batch
+        const size_t lds = single.lds_bytes
+                               ? (size_t)single.lds_bytes
+                               : fma_lds(N, single.t.W, single.t.D, single.ados_per_tile,
+                                         (int)sizeof(T)).total;
         e = batched ? launch_fma_t<T, true>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream)
                     : launch_fma_t<T, false>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream);
         if (e != hipSuccess) g_launch_what = "FMA bulk stage kernel";

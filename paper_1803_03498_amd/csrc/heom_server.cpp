@@ -312,7 +312,11 @@ bool heom_server::rebuild() {
         g.n_jobs = (int)kv.second.size();
         g.sizing = *kv.second.front();
         int maxN = 0, maxW = 0, maxD = 0, tiles = 0;
+        size_t fma_bytes = 0;
         for (const heom::Job* j : kv.second) {
+            if (g.nb == 0)
+                fma_bytes = std::max(fma_bytes, heom::fma_lds(j->t.N, j->t.W, j->t.D, j->ados_per_tile,
+                                                              g.precision == HEOM_FP64 ? 8 : 4).total);
             heom::Job c = *j;
             c.tile_begin = tiles;
             tiles += (c.t.n_ado > 1) ? c.n_tiles : 0;
@@ -327,6 +331,7 @@ bool heom_server::rebuild() {
         g.sizing.t.W = maxW;
         g.sizing.t.D = maxD;
         g.sizing.herm = g.herm;
+        g.sizing.lds_bytes = (uint32_t)fma_bytes;
         if (g.nb == 0) g.sizing.t.h_complex = 1;  // selects the FMA path for any N
         groups.push_back(g);
     }
