@@ -43,7 +43,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="aggregate48", choices=sorted(WORKLOADS) + ["serve"])
+    ap.add_argument("--workload", default="aggregate48",
+                    choices=sorted(WORKLOADS) + ["serve", "copy"])
+    ap.add_argument("--copy-gib", type=float, default=4.0,
+                    help="--workload copy: bytes read (and written) per copy")
     ap.add_argument("--precision", default="fp32_mixed", choices=["fp32_mixed", "fp64"])
     ap.add_argument("--cpu-baseline-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle sample (0 disables it)")
@@ -185,8 +188,35 @@ def run_serve(args):
     print(json.dumps(line), flush=True)
 
 
+def run_copy(args):
+    """A plain device-to-device copy of known size: the reference against
+    which the HBM byte counters of a profiler run are scaled."""
+    import torch
+    torch.cuda.set_device(0)
+    n = int(args.copy_gib * (1 << 30)) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    steps = args.steps if args.steps is not None else 20
+    warmup = args.warmup if args.warmup is not None else 3
+    for _ in range(warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    print(json.dumps({"workload": "copy", "bytes_read_per_copy": 4 * n,
+                      "bytes_written_per_copy": 4 * n, "steps": steps,
+                      "ms_per_copy": 1e3 * el / steps,
+                      "GBps_read_plus_write": 8 * n * steps / el / 1e9}), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "copy":
+        run_copy(args)
+        return
     if args.workload == "serve":
         if args.gpus != 1:
             print("bench.py runs on one GPU only (--gpus %d requested)" % args.gpus,
@@ -234,6 +264,8 @@ def main():
     kbytes = ctypes.c_double()
     lib.heom_timing_read(ctypes.byref(ms), ctypes.byref(launches), ctypes.byref(kbytes), 1)
 
+    kernel_name = ("k_bulk_mfma" if info["bulk_kernel"] else "k_bulk_fma") + \
+        " (RK4 stage, ADOs u>=1)"
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / steps
     ado_updates = n * steps / elapsed
@@ -278,7 +310,7 @@ def main():
             "bytes_per_step_algorithmic": step_bytes,
         },
         "roofline": {
-            "kernel": "k_bulk_fma (RK4 stage, ADOs u>=1)",
+            "kernel": kernel_name,
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -113,6 +113,9 @@ typedef struct {
     size_t rest_bytes;      /* (n_ado - 1) * N*N * elem_bytes             */
     size_t work_bytes;      /* device workspace of heom_propagate without
                                records (three RK4 stage copies + control) */
+    int32_t bulk_kernel;    /* stage kernel of ADOs u >= 1: 1 = matrix-core
+                               commutator (real H, N >= 16), 0 = FMA       */
+    int32_t reserved;
 } heom_info;
 
 /* A hierarchy state: sigma_0 (complex128 [N][N]) and ADOs 1..n_ado-1

@@ -38,7 +38,8 @@ class HeomInfo(ctypes.Structure):
                 ("n_states", ctypes.c_int32), ("n_modes", ctypes.c_int32),
                 ("depth", ctypes.c_int32), ("elem_bytes", ctypes.c_int32),
                 ("tables_bytes", ctypes.c_size_t), ("sigma0_bytes", ctypes.c_size_t),
-                ("rest_bytes", ctypes.c_size_t), ("work_bytes", ctypes.c_size_t)]
+                ("rest_bytes", ctypes.c_size_t), ("work_bytes", ctypes.c_size_t),
+                ("bulk_kernel", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class HeomState(ctypes.Structure):

@@ -69,7 +69,7 @@ struct Derived {
 struct Layout {
     size_t h_re, h_im, mode_site, mode_gamma, mode_c, mode_lamnu, plus_coef, minus_coef,
         delta_state, state_mode_begin, state_modes, binom, consts_end;
-    size_t tuples, level, plus, minus, mlist, damping, total;
+    size_t tuples, level, plus, minus, mlist, mlist_site, mlist_w, plus_w, damping, total;
 };
 
 Layout make_layout(int N, int W, int D, int64_t n_ado) {
@@ -100,6 +100,9 @@ Layout make_layout(int N, int W, int D, int64_t n_ado) {
     L.plus = take((size_t)n_ado * W * 4);
     L.minus = take((size_t)n_ado * W * 4);
     L.mlist = take((size_t)n_ado * std::max(D, 1) * 8);
+    L.mlist_site = take((size_t)n_ado * std::max(D, 1) * 4);
+    L.mlist_w = take((size_t)n_ado * std::max(D, 1) * 16);
+    L.plus_w = take((size_t)n_ado * W * 8);
     L.damping = take((size_t)n_ado * 8);
     L.total = o;
     return L;
@@ -283,6 +286,7 @@ void fill_info(const Derived& d, heom_info* info) {
     info->sigma0_bytes = NN * 16;
     info->rest_bytes = (size_t)(d.n_ado - 1) * NN * info->elem_bytes;
     // control block (step counter, status, mu) + three stage copies
+    info->bulk_kernel = heom::bulk_mfma_blocks(d.N, d.h_complex, d.precision) > 0 ? 1 : 0;
     info->work_bytes = 1024 + align256(d.N * 8) +
                        3 * (align256(info->sigma0_bytes) + align256(std::max<size_t>(info->rest_bytes, 1)));
 }
@@ -422,6 +426,9 @@ heom_status heom_build_hierarchy(const heom_problem* problem, void* tables_dev,
     t.plus = reinterpret_cast<int32_t*>(base + L.plus);
     t.minus = reinterpret_cast<int32_t*>(base + L.minus);
     t.mlist = reinterpret_cast<int32_t*>(base + L.mlist);
+    t.mlist_site = reinterpret_cast<int32_t*>(base + L.mlist_site);
+    t.mlist_w = reinterpret_cast<double*>(base + L.mlist_w);
+    t.plus_w = reinterpret_cast<double*>(base + L.plus_w);
     t.damping = reinterpret_cast<double*>(base + L.damping);
 
     hipStream_t st = static_cast<hipStream_t>(stream);

@@ -130,18 +130,23 @@ __global__ __launch_bounds__(256) void k_links(Tables t) {
     const int u = (int)(idx / W);
     const int l = (int)(idx - (int64_t)u * W);
     const gptr<uint8_t> n = G(t.tuples) + (size_t)u * W;
-    G(t.plus)[idx] = (G(t.level)[u] < t.D) ? (int32_t)rank_with(n, W, G(t.binom), l, +1) : -1;
+    const bool up = G(t.level)[u] < t.D;
+    G(t.plus)[idx] = up ? (int32_t)rank_with(n, W, G(t.binom), l, +1) : -1;
+    G(t.plus_w)[idx] = up ? G(t.plus_coef)[(size_t)l * (t.D + 1) + n[l]] : 0.0;
     G(t.minus)[idx] = (n[l] > 0) ? (int32_t)rank_with(n, W, G(t.binom), l, -1) : -1;
 }
 
 // Compact list of the active "-" links of every ADO (n_l > 0; at most D of
-// them since |n| <= D), in mode order, padded with -1.  The stage kernels read
-// one row of it instead of walking the tuple.
+// them since |n| <= D), in mode order, padded with -1, with the state and the
+// two weights of each link.  The stage kernels read one row of it instead of
+// walking the tuple.
 __global__ __launch_bounds__(256) void k_minus_list(Tables t) {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= t.n_ado) return;
     const int W = t.W, Dm = t.D > 0 ? t.D : 1;
     gptr<pair_i> out = G(reinterpret_cast<pair_i*>(t.mlist)) + (size_t)u * Dm;
+    gptr<int32_t> site = G(t.mlist_site) + (size_t)u * Dm;
+    gptr<pair_d> wt = G(reinterpret_cast<pair_d*>(t.mlist_w)) + (size_t)u * Dm;
     int k = 0;
     for (int l = 0; l < W && k < Dm; ++l) {
         const int nl = G(t.tuples)[(size_t)u * W + l];
@@ -149,6 +154,12 @@ __global__ __launch_bounds__(256) void k_minus_list(Tables t) {
             pair_i v;
             v.x = G(t.minus)[(size_t)u * W + l];
             v.y = l | (nl << 8);
+            const double b = G(t.minus_coef)[(size_t)l * (t.D + 1) + nl];
+            pair_d w;
+            w.x = b * G(t.mode_lamnu)[l];
+            w.y = b * G(t.mode_c)[l];
+            site[k] = G(t.mode_site)[l];
+            wt[k] = w;
             out[k++] = v;
         }
     }
@@ -156,6 +167,11 @@ __global__ __launch_bounds__(256) void k_minus_list(Tables t) {
         pair_i v;
         v.x = -1;
         v.y = 0;
+        pair_d w;
+        w.x = 0.0;
+        w.y = 0.0;
+        site[k] = -1;
+        wt[k] = w;
         out[k] = v;
     }
 }
@@ -633,18 +649,30 @@ constexpr int kPrefRows = 4;
 template <typename T, int NB, bool HERM>
 struct MfmaLds {
     static constexpr int NP = 16 * NB;
-    // sigma (and Y) planes: rows 16 banks apart, so the four rows of an MFMA
+    // sigma planes: rows 16 banks apart, so the four rows of an MFMA
     // B-operand read fall in distinct banks
     static constexpr int LS = (NP % 32 == 16) ? NP : NP + 16;
-    // X planes: odd stride, so the transposed reads X[j][i] hit distinct banks
+    // X and coupling planes: odd stride, so transposed reads [j][i] hit distinct banks
     static constexpr int LX = NP + 1;
-    static constexpr int PLANE = NP * LS;
     static constexpr int XPLANE = NP * LX;
+    // a sigma plane also holds a coupling plane of stride LX
+    static constexpr int PLANE = NP * LS > XPLANE ? NP * LS : XPLANE;
+    __host__ __device__ static int n_rows(int D) {
+        const int Dm = D > 0 ? D : 1;
+        return Dm < kPrefRows ? Dm : kPrefRows;
+    }
+    // Layout: T planes (sigma, then couplings; X; Y on the general path),
+    // prefetched "-" rows (T), "+" neighbour tile addresses (8 bytes each),
+    // T: "-" weights, per-state correction, "+" weights; int: per-state mode
+    // lists, "-" state and neighbour.  Every block before the addresses is a
+    // multiple of 8 bytes.
+    __host__ __device__ static size_t t_head(int N, int D) {
+        return (size_t)PLANE * (HERM ? 2 : 4) + 2 * (size_t)XPLANE + 2 * (size_t)n_rows(D) * N;
+    }
     __host__ __device__ static size_t bytes(int N, int W, int D) {
         const int Dm = D > 0 ? D : 1;
-        return sizeof(T) * ((size_t)PLANE * (HERM ? 2 : 4) + 2 * (size_t)XPLANE +
-                            2 * kPrefRows * NP + 2 * (size_t)Dm + N + W) +
-               4 * (2 * (size_t)Dm + W);
+        return sizeof(T) * t_head(N, D) + 8 * (size_t)W + sizeof(T) * (2 * (size_t)Dm + N + W) +
+               4 * ((size_t)(N + 1) + W + 2 * (size_t)Dm);
     }
 };
 
@@ -660,67 +688,86 @@ __device__ __forceinline__ double uniform(double x) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Waves per SIMD to ask of the register allocator: four 6-wave workgroups of
-// the FP32 N <= 48 kernel fill a CU's 160 KiB of LDS, which needs <= 80 VGPRs.
-template <typename T, int NB>
+// Waves per SIMD to ask of the register allocator for N <= 48: four 6-wave
+// FP32 workgroups per CU fit the LDS (Hermitian path), two FP64 ones; the
+// general path holds more values in flight.
+template <typename T, int NB, bool HERM>
 constexpr int mfma_waves_per_eu() {
-    return (sizeof(T) == 4 && NB == 3) ? 6 : 1;
+    return NB == 3 ? (sizeof(T) == 4 ? (HERM ? 6 : 4) : (HERM ? 3 : 2)) : 1;
 }
 
-template <typename T, int NB, bool HERM, bool BATCHED>
+// Bulk RK4 stage on the matrix cores, one ADO per workgroup.  Two
+// wavefronts per 16-row block of H: wave (mt, half) computes rows
+// 16 mt .. 16 mt + 15 of X = H Re(sigma) (half 0) or H Im(sigma) (half 1).
+// Thread tid owns column j = tid % NP and rows i = tid / NP + 8 k, k < 2 NB,
+// of the padded NP x NP tile.
+//
+// The coupling terms of the HEOM equation touch only row s and column s of a
+// neighbour, s the state of the mode.  On the Hermitian path the workgroup
+// forms, for every state s with a link, the row
+//   Z[s][c] = sum over "-" links a of state s of (lambda nu_a + i c_a) w_a sigma_{u-e_a}[s][c]
+//           + sum over "+" modes l of state s of i w_l sigma_{u+e_l}[s][c],
+// and element (i, j), i != j, takes Z[i][j] + conj(Z[j][i]), because column s
+// of a Hermitian neighbour is the conjugate of its row s.  The diagonal takes
+// the "-" terms 2 lambda nu_a w_a sigma_{u-e_a}[i][i], kept in Z[i][i].  On the
+// general path element (i, j) forms its whole coupling sum at (i, j).  Z
+// reuses the sigma planes: each thread keeps its sigma elements in registers.
+template <typename T, int NB, bool HERM, bool BATCHED, int NBASE>
 __global__ __launch_bounds__(128 * NB) __attribute__((amdgpu_waves_per_eu(
-    mfma_waves_per_eu<T, NB>()))) void k_bulk_mfma(Job single, const Job* jobs, int n_jobs,
-                                                   StageSpec sp) {
-    // Two wavefronts per 16-row block of H: wave (mt, half) computes rows
-    // 16 mt .. 16 mt + 15 of X = H Re(sigma) (half 0) or H Im(sigma) (half 1).
+    mfma_waves_per_eu<T, NB, HERM>()))) void k_bulk_mfma(Job single, const Job* jobs, int n_jobs,
+                                                          StageSpec sp) {
     constexpr int NT = 128 * NB;
     using L = MfmaLds<T, NB, HERM>;
     constexpr int NP = L::NP, LS = L::LS, LX = L::LX, PLANE = L::PLANE, XPLANE = L::XPLANE;
-    constexpr int KS = 4 * NB;                        // k-steps of 4
-    constexpr int EPT = (NP * NP + NT - 1) / NT;      // elements per thread (2 NB)
+    constexpr int KS = 4 * NB;      // k-steps of 4
+    constexpr int EPT = 2 * NB;     // rows per thread
+    constexpr int RS = NT / NP;     // row step (8)
+    constexpr int KP = 2;           // "+" modes per state loaded ahead (more are read late)
+    constexpr int KX = HERM ? KP : 2 * KP;
     using acc_t = typename mfma_acc<T>::type;
+    using C = cpx<T>;
 
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const Job& J = JobOf<BATCHED>::get(single, jobs, n_jobs, b);
-    const Tables& t = J.t;
-    const int N = t.N, NN = N * N, W = t.W, D = t.D, Dm = D > 0 ? D : 1;
-    const int u = 1 + (b - J.tile_begin);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int mt = wave >> 1, half = wave & 1;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const Job& J = JobOf<BATCHED>::get(single, jobs, n_jobs, tile);
+    const Tables& t = J.t;
+    const int N = t.N, NN = N * N, W = t.W, D = t.D, Dm = D > 0 ? D : 1;
+    const int u = 1 + (tile - J.tile_begin);
+    const char* rest_in = reinterpret_cast<const char*>(J.rest[sp.in]);
+    const size_t tile_bytes = (size_t)NN * sizeof(C);
+    const char* own = rest_in + (size_t)(u - 1) * tile_bytes;
+    const NbSrc<T> nbs{J.sig0[sp.in], J.rest[sp.in], N};
+    const int n_rows = L::n_rows(D);
 
     extern __shared__ char smem_raw[];
-    T* sSre = reinterpret_cast<T*>(smem_raw);
+    T* sSre = reinterpret_cast<T*>(smem_raw);  // sigma (stride LS), then Z (stride LX)
     T* sSim = sSre + PLANE;
     T* sXre = sSim + PLANE;  // stride LX
     T* sXim = sXre + XPLANE;
     T* sYre = sXim + XPLANE;  // general path only
     T* sYim = sYre + PLANE;
-    T* sRow = HERM ? sYre : sYim + PLANE;  // kPrefRows x NP complex
-    T* sMml = sRow + 2 * kPrefRows * NP;          // [Dm] lambda nu weight of "-" link a
-    T* sMmc = sMml + Dm;                          // [Dm] c weight
-    T* sDelta = sMmc + Dm;                        // [N]
-    T* sPa = sDelta + N;                          // [W] "+" weights (level < D only)
-    int* sMsite = reinterpret_cast<int*>(sPa + W);  // [Dm]
+    T* sRow = HERM ? sYre : sYim + PLANE;  // n_rows x N complex
+    const char** sPptr = reinterpret_cast<const char**>(sRow + 2 * n_rows * N);  // [W]
+    T* sMml = reinterpret_cast<T*>(sPptr + W);  // [Dm] "-" weights
+    T* sMmc = sMml + Dm;
+    T* sDelta = sMmc + Dm;  // [N]
+    T* sPa = sDelta + N;    // [W] "+" weights
+    int* sBegin = reinterpret_cast<int*>(sPa + W);  // [N+1]
+    int* sModes = sBegin + N + 1;                   // [W]
+    int* sMsite = sModes + W;                       // [Dm]
     int* sMnb = sMsite + Dm;                        // [Dm]
-    int* sPnb = sMnb + Dm;                          // [W]
 
-    // 1. Independent loads first: link list, own tile, H block of this wave.
-    const int lev = G(t.level)[u];
-    const T gam = (T)G(t.damping)[u];
-    pair_i ml;
-    ml.x = -1;
-    ml.y = 0;
-    if (tid < Dm) ml = G(reinterpret_cast<const pair_i*>(t.mlist))[(size_t)u * Dm + tid];
-    const size_t base = (size_t)(u - 1) * NN;
-    cpx<T> own[EPT];
-    {
-        const void* in = J.rest[sp.in];
+    const int r0 = tid / NP, j = tid - (tid / NP) * NP;
+    const bool jin = j < N;
+
+    // 1. Independent loads: this ADO's tile, its link tables, this wave's block of H.
+    C cur[EPT];
 #pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-            const int e = tid + q * NT;
-            own[q] = (e < NN) ? ld<T>(in, base + e) : cpx<T>{(T)0, (T)0};
-        }
+    for (int k = 0; k < EPT; ++k) {
+        const int i = r0 + RS * k;
+        cur[k] = (jin && i < N) ? ld<T>(own, i * N + j) : C{(T)0, (T)0};
     }
     T hreg[KS];  // A operand: H[16 mt + lane%16][4 ks + lane/16]
 #pragma unroll
@@ -728,74 +775,66 @@ __global__ __launch_bounds__(128 * NB) __attribute__((amdgpu_waves_per_eu(
         const int r = 16 * mt + (lane & 15), c = 4 * ks + (lane >> 4);
         hreg[ks] = (r < N && c < N) ? (T)G(t.h_re)[r * N + c] : (T)0;
     }
-
-    // 2. LDS: own tile planes, link weights, per-state correction, "+" links.
-    const float invN = 1.0f / (float)N;  // exact row index for e < 4096 (N <= 64)
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-        const int e = tid + q * NT;
-        if (e < NN) {
-            const int i = (int)(((float)e + 0.5f) * invN), j = e - i * N;
-            sSre[i * LS + j] = own[q].re;
-            sSim[i * LS + j] = own[q].im;
-        }
+    const int lev = G(t.level)[u];
+    const T gam = (T)G(t.damping)[u];
+    const bool has_plus = lev < D;
+    for (int a = tid; a < Dm; a += NT) {
+        const pair_d w = G(reinterpret_cast<const pair_d*>(t.mlist_w))[(size_t)u * Dm + a];
+        sMnb[a] = G(reinterpret_cast<const pair_i*>(t.mlist))[(size_t)u * Dm + a].x;
+        sMsite[a] = G(t.mlist_site)[(size_t)u * Dm + a];
+        sMml[a] = (T)w.x;
+        sMmc[a] = (T)w.y;
     }
-    if (N < NP) {
-        for (int idx = tid; idx < NP * NP; idx += NT) {
-            const int r = idx / NP, c = idx - (idx / NP) * NP;
-            if (r >= N || c >= N) {
-                sSre[r * LS + c] = (T)0;
-                sSim[r * LS + c] = (T)0;
-            }
+    if (has_plus) {
+        for (int l = tid; l < W; l += NT) {
+            const int nb = G(t.plus)[(size_t)u * W + l];
+            sPptr[l] = rest_in + (size_t)(nb - 1) * tile_bytes;
+            sPa[l] = (T)G(t.plus_w)[(size_t)u * W + l];
+            sModes[l] = G(t.state_modes)[l];
         }
-    }
-    if (tid < Dm) {
-        const int nb = ml.x, mode = ml.y & 255, nl = ml.y >> 8;
-        sMnb[tid] = nb;
-        if (nb >= 0) {
-            const double coef = G(t.minus_coef)[mode * (D + 1) + nl];
-            sMsite[tid] = G(t.mode_site)[mode];
-            sMml[tid] = (T)(coef * G(t.mode_lamnu)[mode]);
-            sMmc[tid] = (T)(coef * G(t.mode_c)[mode]);
-        } else {
-            sMsite[tid] = -1;
-        }
+        for (int x = tid; x <= N; x += NT) sBegin[x] = G(t.state_mode_begin)[x];
     }
     for (int x = tid; x < N; x += NT) sDelta[x] = (T)G(t.delta_state)[x];
-    if (lev < D) {
-        for (int l = tid; l < W; l += NT) {
-            const int nl = G(t.tuples)[(size_t)u * W + l];
-            sPnb[l] = G(t.plus)[(size_t)u * W + l];
-            sPa[l] = (T)G(t.plus_coef)[l * (D + 1) + nl];
-        }
+    // sigma planes, zero outside the N x N block
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int i = r0 + RS * k;
+        sSre[i * LS + j] = cur[k].re;
+        sSim[i * LS + j] = cur[k].im;
     }
     __syncthreads();
 
-    // 3. Prefetch the row s of the first "-" neighbours (Hermitian path) and
-    //    the stage bases; both land while the matrix cores run.
-    const NbSrc<T> nbs{J.sig0[sp.in], J.rest[sp.in], N};
-    const int n_pref = HERM ? min(Dm, kPrefRows) : 0;
-    cpx<T> pre = {(T)0, (T)0};
-    const bool has_pre = tid < n_pref * N && sMnb[tid / N] >= 0;
+    // 2. In flight during the matrix cores: the "-" neighbour rows
+    //    (Hermitian path) and the "+" neighbour values of this thread's elements.
+    C pre = {(T)0, (T)0};
+    const bool has_pre = HERM && tid < n_rows * N && sMnb[tid / N] >= 0;
     if (has_pre) {
         const int a = tid / N, c = tid - (tid / N) * N;
         pre = load_nb<T>(nbs, sMnb[a], sMsite[a], c);
     }
-    cpx<T> bv[3][EPT];
+    C xp[EPT][KX];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        if (m < sp.nbase) {
-            const void* bp = J.rest[sp.base[m]];
+    for (int k = 0; k < EPT; ++k)
 #pragma unroll
-            for (int q = 0; q < EPT; ++q) {
-                const int e = tid + q * NT;
-                bv[m][q] = (e < NN) ? ld<T>(bp, base + e) : cpx<T>{(T)0, (T)0};
+        for (int q = 0; q < KX; ++q) xp[k][q] = {(T)0, (T)0};
+    if (has_plus && jin) {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int i = r0 + RS * k;
+            if (i < N && i != j) {
+#pragma unroll
+                for (int q = 0; q < KX; ++q) {
+                    // Hermitian: modes of state i; general: modes of state i,
+                    // then of state j; all at (i, j)
+                    const int s = (q < KP) ? i : j, qq = (q < KP) ? q : q - KP;
+                    const int m0 = sBegin[s];
+                    if (qq < sBegin[s + 1] - m0) xp[k][q] = ld<T>(sPptr[sModes[m0 + qq]], i * N + j);
+                }
             }
         }
     }
 
-    // 4. X = H [Re S | Im S]: this wave's 16-row block against every column block.
-    const int ksteps = (N + 3) >> 2;
+    // 3. X = H [Re S | Im S]: this wave's 16-row block against every column block.
     {
         const T* plane = half ? sSim : sSre;
         T* out = half ? sXim : sXre;
@@ -804,10 +843,8 @@ __global__ __launch_bounds__(128 * NB) __attribute__((amdgpu_waves_per_eu(
             acc_t acc = {0, 0, 0, 0};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
-                if (ks < ksteps) {
-                    const T bval = plane[(4 * ks + (lane >> 4)) * LS + 16 * cb + (lane & 15)];
-                    acc = mfma16(hreg[ks], bval, acc);
-                }
+                const T bval = plane[(4 * ks + (lane >> 4)) * LS + 16 * cb + (lane & 15)];
+                acc = mfma16(hreg[ks], bval, acc);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r)
@@ -815,39 +852,37 @@ __global__ __launch_bounds__(128 * NB) __attribute__((amdgpu_waves_per_eu(
         }
     }
     if (!HERM) {
-        // Y = S H: wave w takes row block w of [Re S; Im S] (2 NB blocks, one per
-        // wave); H (real symmetric) as the B operand, read per column block.
+        // Y = S H: wave w takes row block w of [Re S; Im S]; H (real
+        // symmetric) as the B operand, read per column block.
         const T* plane = wave < NB ? sSre : sSim;
         T* out = wave < NB ? sYre : sYim;
-        const int r0 = 16 * (wave < NB ? wave : wave - NB);
+        const int rb = 16 * (wave < NB ? wave : wave - NB);
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb) {
             acc_t acc = {0, 0, 0, 0};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
-                if (ks < ksteps) {
-                    const int kr = 4 * ks + (lane >> 4), jc = 16 * cb + (lane & 15);
-                    const T hb = (kr < N && jc < N) ? (T)G(t.h_re)[kr * N + jc] : (T)0;
-                    const T av = plane[(r0 + (lane & 15)) * LS + 4 * ks + (lane >> 4)];
-                    acc = mfma16(av, hb, acc);
-                }
+                const int kr = 4 * ks + (lane >> 4), jc = 16 * cb + (lane & 15);
+                const T hb = (kr < N && jc < N) ? (T)G(t.h_re)[kr * N + jc] : (T)0;
+                const T av = plane[(rb + (lane & 15)) * LS + 4 * ks + (lane >> 4)];
+                acc = mfma16(av, hb, acc);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                out[(r0 + mfma_row<T>(lane, r)) * LS + 16 * cb + (lane & 15)] = acc[r];
+                out[(rb + mfma_row<T>(lane, r)) * LS + 16 * cb + (lane & 15)] = acc[r];
         }
     }
     if (has_pre) {
         sRow[2 * tid] = pre.re;
         sRow[2 * tid + 1] = pre.im;
     }
-    __syncthreads();
+    __syncthreads();  // sigma planes are free from here on
 
-    // 5. Elementwise lines: -i[H, sigma], damping, correction, couplings.  A
-    //    thread reads only its own elements of the sigma planes here, so the
-    //    value w_in * sigma + h * f goes back into the same slots.  The first
-    //    kPrefRows "-" links are wave-uniform and held in scalar registers.
-    const T h = (T)(sp.hmul * J.dt), w_in = (T)sp.w_in;
+    // 4. Coupling sums Z into the sigma planes; the stage bases in flight.
+    //    The first kPrefRows "-" links are wave-uniform (scalar registers);
+    //    mmask marks the states with a "-" link.
+    T* sZre = sSre;
+    T* sZim = sSim;
     int lsite[kPrefRows];
     T lml[kPrefRows], lmc[kPrefRows];
 #pragma unroll
@@ -856,87 +891,137 @@ __global__ __launch_bounds__(128 * NB) __attribute__((amdgpu_waves_per_eu(
         lml[a] = uniform(a < Dm ? sMml[a] : (T)0);
         lmc[a] = uniform(a < Dm ? sMmc[a] : (T)0);
     }
-#pragma unroll 2
-    for (int e = tid; e < NN; e += NT) {
-        const int i = (int)(((float)e + 0.5f) * invN), j = e - i * N;
-        T cr, ci;
+    uint64_t mmask = 0;
+#pragma unroll
+    for (int a = 0; a < kPrefRows; ++a)
+        if (lsite[a] >= 0) mmask |= 1ull << lsite[a];
+    for (int a = kPrefRows; a < Dm; ++a) {
+        const int s = uniform(sMsite[a]);
+        if (s >= 0) mmask |= 1ull << s;
+    }
+    if (jin) {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int i = r0 + RS * k;
+            if (i >= N) continue;
+            T zr = 0, zi = 0;
+            if (has_plus && i != j) {
+#pragma unroll
+                for (int pass = 0; pass < (HERM ? 1 : 2); ++pass) {
+                    const int s = pass == 0 ? i : j;
+                    const int m0 = sBegin[s], cnt = sBegin[s + 1] - m0;
+                    T pr = 0, pi = 0;
+#pragma unroll
+                    for (int q = 0; q < KP; ++q) {
+                        if (q < cnt) {
+                            const T w = sPa[sModes[m0 + q]];
+                            pr += w * xp[k][pass * KP + q].re;
+                            pi += w * xp[k][pass * KP + q].im;
+                        }
+                    }
+                    for (int q = KP; q < cnt; ++q) {
+                        const int l = sModes[m0 + q];
+                        const C x = ld<T>(sPptr[l], i * N + j);
+                        pr += sPa[l] * x.re;
+                        pi += sPa[l] * x.im;
+                    }
+                    // i * w * (V^x x): +1 for the modes of state i, -1 for those of j
+                    if (pass == 0) {
+                        zr -= pi;
+                        zi += pr;
+                    } else {
+                        zr += pi;
+                        zi -= pr;
+                    }
+                }
+            }
+            const bool row_i = (mmask >> i) & 1;
+            const bool row_j = !HERM && ((mmask >> j) & 1);
+            if (row_i || row_j) {
+                // "-" link a of state s with weights (ml, mc) on element (i, j)
+                auto minus = [&](int a, int s, T ml, T mc) {
+                    if (HERM) {
+                        if (s != i) return;
+                        const C x = a < n_rows ? C{sRow[2 * (a * N + j)], sRow[2 * (a * N + j) + 1]}
+                                               : load_nb<T>(nbs, sMnb[a], i, j);
+                        if (i == j) {
+                            zr += 2 * ml * x.re;
+                            zi += 2 * ml * x.im;
+                        } else {
+                            zr += ml * x.re - mc * x.im;
+                            zi += ml * x.im + mc * x.re;
+                        }
+                    } else {
+                        if (s != i && s != j) return;
+                        const C x = load_nb<T>(nbs, sMnb[a], i, j);
+                        const T vx = (T)((i == s) - (j == s)), vo = (T)((i == s) + (j == s));
+                        const T thr = ml * vo, thi = mc * vx;
+                        zr += thr * x.re - thi * x.im;
+                        zi += thr * x.im + thi * x.re;
+                    }
+                };
+#pragma unroll
+                for (int a = 0; a < kPrefRows; ++a)
+                    if (lsite[a] >= 0) minus(a, lsite[a], lml[a], lmc[a]);
+                for (int a = kPrefRows; a < Dm; ++a)
+                    if (sMsite[a] >= 0) minus(a, sMsite[a], sMml[a], sMmc[a]);
+            }
+            sZre[i * LX + j] = zr;
+            sZim[i * LX + j] = zi;
+        }
+    }
+    C bv[NBASE][EPT];
+#pragma unroll
+    for (int m = 0; m < NBASE; ++m) {
+        if (m < sp.nbase) {
+            const char* bp = reinterpret_cast<const char*>(J.rest[sp.base[m]]) + (size_t)(u - 1) * tile_bytes;
+#pragma unroll
+            for (int k = 0; k < EPT; ++k) {
+                const int i = r0 + RS * k;
+                bv[m][k] = (jin && i < N) ? ld<T>(bp, i * N + j) : C{(T)0, (T)0};
+            }
+        }
+    }
+    __syncthreads();
+
+    // 5. Elementwise: -i[H, sigma], damping, correction, couplings, and the
+    //    stage combination.
+    if (!jin) return;
+    const T h = (T)(sp.hmul * J.dt), w_in = (T)sp.w_in;
+    char* outp = reinterpret_cast<char*>(J.rest[sp.out]) + (size_t)(u - 1) * tile_bytes;
+    const T dj = sDelta[j];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int i = r0 + RS * k;
+        if (i >= N) continue;
+        const bool off = i != j;
+        T cr, ci, zr, zi;
         if (HERM) {
             cr = sXre[i * LX + j] - sXre[j * LX + i];
             ci = sXim[i * LX + j] + sXim[j * LX + i];
+            zr = sZre[i * LX + j] + (off ? sZre[j * LX + i] : (T)0);
+            zi = sZim[i * LX + j] - (off ? sZim[j * LX + i] : (T)0);
         } else {
             cr = sXre[i * LX + j] - sYre[i * LS + j];
             ci = sXim[i * LX + j] - sYim[i * LS + j];
+            zr = sZre[i * LX + j];
+            zi = sZim[i * LX + j];
         }
-        const T sr = sSre[i * LS + j], si = sSim[i * LS + j];
-        const T g = gam + ((i != j) ? sDelta[i] + sDelta[j] : (T)0);
-        T fr = ci - g * sr, fi = -cr - g * si;
+        const T sr = cur[k].re, si = cur[k].im;
+        const T g = gam + (off ? sDelta[i] + dj : (T)0);
+        const T fr = ci - g * sr + zr, fi = -cr - g * si + zi;
+        T yr = w_in * sr + h * fr, yi = w_in * si + h * fi;
 #pragma unroll
-        for (int a = 0; a < kPrefRows; ++a) {
-            const int s = lsite[a];
-            if (s < 0 || (i != s && j != s)) continue;
-            const bool col = (j == s) && (i != s);
-            cpx<T> x;
-            if (HERM) {
-                const int c = col ? i : j;  // Hermitian: column s is conj(row s)
-                x = {sRow[2 * (a * N + c)], sRow[2 * (a * N + c) + 1]};
-                if (col) x = cconj(x);
-            } else {
-                x = load_nb<T>(nbs, sMnb[a], i, j);
-            }
-            const T vx = (T)((i == s) - (j == s)), vo = (T)((i == s) + (j == s));
-            const T thr = lml[a] * vo, thi = lmc[a] * vx;
-            fr += thr * x.re - thi * x.im;
-            fi += thr * x.im + thi * x.re;
-        }
-        for (int a = kPrefRows; a < Dm; ++a) {
-            const int s = sMsite[a];
-            if (s < 0 || (i != s && j != s)) continue;
-            const bool col = (j == s) && (i != s);
-            const cpx<T> x = (HERM && col) ? cconj(load_nb<T>(nbs, sMnb[a], s, i))
-                                           : load_nb<T>(nbs, sMnb[a], i, j);
-            const T vx = (T)((i == s) - (j == s)), vo = (T)((i == s) + (j == s));
-            const T thr = sMml[a] * vo, thi = sMmc[a] * vx;
-            fr += thr * x.re - thi * x.im;
-            fi += thr * x.im + thi * x.re;
-        }
-        if (lev < D && i != j) {
-            for (int pass = 0; pass < 2; ++pass) {
-                const int s = pass == 0 ? i : j;
-                for (int m = G(t.state_mode_begin)[s]; m < G(t.state_mode_begin)[s + 1]; ++m) {
-                    const int l = G(t.state_modes)[m];
-                    const int nb = sPnb[l];
-                    const cpx<T> x = (HERM && pass == 1) ? cconj(load_nb<T>(nbs, nb, s, i))
-                                                         : load_nb<T>(nbs, nb, i, j);
-                    const T pa = pass == 0 ? sPa[l] : -sPa[l];  // i * pa * vx * x
-                    fr -= pa * x.im;
-                    fi += pa * x.re;
-                }
+        for (int m = 0; m < NBASE; ++m) {
+            if (m < sp.nbase) {
+                const T w = (T)sp.wbase[m];
+                yr += w * bv[m][k].re;
+                yi += w * bv[m][k].im;
             }
         }
-        sSre[i * LS + j] = w_in * sr + h * fr;
-        sSim[i * LS + j] = w_in * si + h * fi;
-    }
-
-    // 6. RK4 stage combination with the prefetched bases, then the stores.
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-        const int e = tid + q * NT;
-        if (e < NN) {
-            const int i = (int)(((float)e + 0.5f) * invN), j = e - i * N;
-            T yr = sSre[i * LS + j], yi = sSim[i * LS + j];
-#pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                if (m < sp.nbase) {
-                    const T w = (T)sp.wbase[m];
-                    yr += w * bv[m][q].re;
-                    yi += w * bv[m][q].im;
-                }
-            }
-            st<T>(J.rest[sp.out], base + e, cpx<T>{yr, yi});
-        }
+        st<T>(outp, i * N + j, C{yr, yi});
     }
 }
-
 
 }  // namespace
 
@@ -967,21 +1052,31 @@ hipError_t launch_enumerate(const Tables& t, hipStream_t stream) {
     return hipGetLastError();
 }
 
-template <typename T, int NB, bool HERM, bool BATCHED>
+template <typename T, int NB, bool HERM, bool BATCHED, int NBASE>
 static hipError_t launch_mfma_t(const Job& single, const Job* jobs_dev, int n_jobs,
                                 int total_tiles, const StageSpec& sp, hipStream_t stream) {
+    const void* fn = reinterpret_cast<const void*>(&k_bulk_mfma<T, NB, HERM, BATCHED, NBASE>);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t a = hipFuncSetAttribute(
-            reinterpret_cast<const void*>(&k_bulk_mfma<T, NB, HERM, BATCHED>),
-            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipError_t a =
+            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (a != hipSuccess) return a;
         attr_set = true;
     }
     const size_t lds = MfmaLds<T, NB, HERM>::bytes(single.t.N, single.t.W, single.t.D);
-    hipLaunchKernelGGL((k_bulk_mfma<T, NB, HERM, BATCHED>), dim3(total_tiles), dim3(128 * NB),
-                       lds, stream, single, jobs_dev, n_jobs, sp);
+    hipLaunchKernelGGL((k_bulk_mfma<T, NB, HERM, BATCHED, NBASE>), dim3(total_tiles),
+                       dim3(128 * NB), lds, stream, single, jobs_dev, n_jobs, sp);
     return hipGetLastError();
+}
+
+template <typename T, int NB, bool HERM, bool BATCHED>
+static hipError_t launch_mfma_b(const Job& single, const Job* jobs_dev, int n_jobs,
+                                int total_tiles, const StageSpec& sp, hipStream_t stream) {
+    if (sp.nbase <= 1)
+        return launch_mfma_t<T, NB, HERM, BATCHED, 1>(single, jobs_dev, n_jobs, total_tiles, sp,
+                                                      stream);
+    return launch_mfma_t<T, NB, HERM, BATCHED, 3>(single, jobs_dev, n_jobs, total_tiles, sp,
+                                                  stream);
 }
 
 template <typename T, int NB>
@@ -989,13 +1084,13 @@ static hipError_t launch_mfma_nb(bool herm, bool batched, const Job& single, con
                                  int n_jobs, int total_tiles, const StageSpec& sp,
                                  hipStream_t stream) {
     if (herm)
-        return batched ? launch_mfma_t<T, NB, true, true>(single, jobs_dev, n_jobs, total_tiles, sp,
-                                                          stream)
-                       : launch_mfma_t<T, NB, true, false>(single, jobs_dev, n_jobs, total_tiles,
+        return batched ? launch_mfma_b<T, NB, true, true>(single, jobs_dev, n_jobs, total_tiles,
+                                                          sp, stream)
+                       : launch_mfma_b<T, NB, true, false>(single, jobs_dev, n_jobs, total_tiles,
                                                            sp, stream);
-    return batched ? launch_mfma_t<T, NB, false, true>(single, jobs_dev, n_jobs, total_tiles, sp,
+    return batched ? launch_mfma_b<T, NB, false, true>(single, jobs_dev, n_jobs, total_tiles, sp,
                                                        stream)
-                   : launch_mfma_t<T, NB, false, false>(single, jobs_dev, n_jobs, total_tiles, sp,
+                   : launch_mfma_b<T, NB, false, false>(single, jobs_dev, n_jobs, total_tiles, sp,
                                                         stream);
 }
 
@@ -1008,7 +1103,11 @@ static hipError_t launch_mfma(int nb, bool herm, const Job& single, const Job* j
         case 1: return launch_mfma_nb<T, 1>(herm, batched, single, jobs_dev, n_jobs, total_tiles, sp, stream);
         case 2: return launch_mfma_nb<T, 2>(herm, batched, single, jobs_dev, n_jobs, total_tiles, sp, stream);
         case 3: return launch_mfma_nb<T, 3>(herm, batched, single, jobs_dev, n_jobs, total_tiles, sp, stream);
-        case 4: return launch_mfma_nb<T, 4>(herm, batched, single, jobs_dev, n_jobs, total_tiles, sp, stream);
+        case 4:
+            // FP64 above 48 states takes the FMA kernel (LDS)
+            if constexpr (sizeof(T) == 4)
+                return launch_mfma_nb<T, 4>(herm, batched, single, jobs_dev, n_jobs, total_tiles, sp, stream);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }

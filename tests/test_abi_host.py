@@ -135,3 +135,18 @@ def test_spectrum_closed_form_and_oracle(heom, orc):
     rng = np.random.default_rng(5)
     Pr = rng.normal(size=(3, 300)) + 1j * rng.normal(size=(3, 300))
     assert np.allclose(heom.spectrum(Pr, 2.0, w), orc.spectrum(Pr, 2.0, w), rtol=1e-12, atol=1e-12)
+
+
+def test_bulk_kernel_choice(heom):
+    # matrix cores for real H with N >= 16 (FP64 up to 48 states), FMA otherwise
+    assert heom.plan(hi.aggregate48(), heom.FP32_MIXED)["bulk_kernel"] == 1
+    assert heom.plan(hi.aggregate48(), heom.FP64)["bulk_kernel"] == 1
+    assert heom.plan(hi.aggregate24(), heom.FP32_MIXED)["bulk_kernel"] == 1
+    assert heom.plan(hi.fmo_like(), heom.FP32_MIXED)["bulk_kernel"] == 0
+    big = _bad(hi.dimer(), H=np.eye(64), baths=[])
+    assert heom.plan(big, heom.FP32_MIXED)["bulk_kernel"] == 1
+    assert heom.plan(big, heom.FP64)["bulk_kernel"] == 0
+    cplx = _bad(hi.aggregate24(), H=hi.aggregate24()["H"] * (1 + 0j))
+    cplx["H"][0, 1] += 1j
+    cplx["H"][1, 0] -= 1j
+    assert heom.plan(cplx, heom.FP32_MIXED)["bulk_kernel"] == 0
