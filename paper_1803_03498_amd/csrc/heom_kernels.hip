@@ -688,15 +688,24 @@ __device__ __forceinline__ double uniform(double x) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Waves per SIMD to ask of the register allocator for N <= 48: four 6-wave
-// FP32 workgroups per CU fit the LDS (Hermitian path), two FP64 ones; the
-// general path holds more values in flight.
+// ADOs per workgroup.  FP32 N <= 48 runs two 6-wave halves in one 12-wave
+// workgroup: the waves of a workgroup are spread evenly over the four SIMDs
+// of a CU, and 12 waves (3 per SIMD) pack where 6 (2/2/1/1) leave holes.
+template <typename T, int NB>
+constexpr int mfma_ados_per_wg() {
+    return (sizeof(T) == 4 && NB == 3) ? 2 : 1;
+}
+
+// Waves per SIMD to ask of the register allocator for N <= 48: two 12-wave
+// FP32 workgroups per CU (their LDS fits), two 6-wave FP64 ones; the general
+// path holds more values in flight.
 template <typename T, int NB, bool HERM>
 constexpr int mfma_waves_per_eu() {
     return NB == 3 ? (sizeof(T) == 4 ? (HERM ? 6 : 4) : (HERM ? 3 : 2)) : 1;
 }
 
-// Bulk RK4 stage on the matrix cores, one ADO per workgroup.  Two
+// Bulk RK4 stage on the matrix cores, one ADO per 128 NB threads (a
+// workgroup holds mfma_ados_per_wg of them, each with its own LDS).  Two
 // wavefronts per 16-row block of H: wave (mt, half) computes rows
 // 16 mt .. 16 mt + 15 of X = H Re(sigma) (half 0) or H Im(sigma) (half 1).
 // Thread tid owns column j = tid % NP and rows i = tid / NP + 8 k, k < 2 NB,
@@ -713,10 +722,15 @@ constexpr int mfma_waves_per_eu() {
 // general path element (i, j) forms its whole coupling sum at (i, j).  Z
 // reuses the sigma planes: each thread keeps its sigma elements in registers.
 template <typename T, int NB, bool HERM, bool BATCHED, int NBASE>
-__global__ __launch_bounds__(128 * NB) __attribute__((amdgpu_waves_per_eu(
-    mfma_waves_per_eu<T, NB, HERM>()))) void k_bulk_mfma(Job single, const Job* jobs, int n_jobs,
-                                                          StageSpec sp) {
-    constexpr int NT = 128 * NB;
+__global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute__((
+    amdgpu_waves_per_eu(mfma_waves_per_eu<T, NB, HERM>()))) void k_bulk_mfma(Job single,
+                                                                             const Job* jobs,
+                                                                             int n_jobs,
+                                                                             StageSpec sp,
+                                                                             int total_tiles,
+                                                                             unsigned lds_stride) {
+    constexpr int NT = 128 * NB;  // threads per ADO
+    constexpr int AW = mfma_ados_per_wg<T, NB>();
     using L = MfmaLds<T, NB, HERM>;
     constexpr int NP = L::NP, LS = L::LS, LX = L::LX, PLANE = L::PLANE, XPLANE = L::XPLANE;
     constexpr int KS = 4 * NB;      // k-steps of 4
@@ -727,14 +741,17 @@ __global__ __launch_bounds__(128 * NB) __attribute__((amdgpu_waves_per_eu(
     using acc_t = typename mfma_acc<T>::type;
     using C = cpx<T>;
 
-    const int tid = threadIdx.x;
+    const int sub = AW > 1 ? uniform((int)threadIdx.x / NT) : 0;  // whole waves per half
+    const int tid = (int)threadIdx.x - sub * NT;
     const int lane = tid & 63, wave = tid >> 6;
     const int mt = wave >> 1, half = wave & 1;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const Job& J = JobOf<BATCHED>::get(single, jobs, n_jobs, tile);
+    const int tile = xcd_remap(blockIdx.x, gridDim.x) * AW + sub;
+    // A half without an ADO still takes part in every barrier.
+    const bool active = tile < total_tiles;
+    const Job& J = JobOf<BATCHED>::get(single, jobs, n_jobs, active ? tile : total_tiles - 1);
     const Tables& t = J.t;
     const int N = t.N, NN = N * N, W = t.W, D = t.D, Dm = D > 0 ? D : 1;
-    const int u = 1 + (tile - J.tile_begin);
+    const int u = active ? 1 + (tile - J.tile_begin) : 1;
     const char* rest_in = reinterpret_cast<const char*>(J.rest[sp.in]);
     const size_t tile_bytes = (size_t)NN * sizeof(C);
     const char* own = rest_in + (size_t)(u - 1) * tile_bytes;
@@ -742,7 +759,7 @@ __global__ __launch_bounds__(128 * NB) __attribute__((amdgpu_waves_per_eu(
     const int n_rows = L::n_rows(D);
 
     extern __shared__ char smem_raw[];
-    T* sSre = reinterpret_cast<T*>(smem_raw);  // sigma (stride LS), then Z (stride LX)
+    T* sSre = reinterpret_cast<T*>(smem_raw + (size_t)sub * lds_stride);  // sigma (stride LS), then Z (stride LX)
     T* sSim = sSre + PLANE;
     T* sXre = sSim + PLANE;  // stride LX
     T* sXim = sXre + XPLANE;
@@ -760,7 +777,7 @@ __global__ __launch_bounds__(128 * NB) __attribute__((amdgpu_waves_per_eu(
     int* sMnb = sMsite + Dm;                        // [Dm]
 
     const int r0 = tid / NP, j = tid - (tid / NP) * NP;
-    const bool jin = j < N;
+    const bool jin = active && j < N;  // this thread's column is stored
 
     // 1. Independent loads: this ADO's tile, its link tables, this wave's block of H.
     C cur[EPT];
@@ -1063,9 +1080,12 @@ static hipError_t launch_mfma_t(const Job& single, const Job* jobs_dev, int n_jo
         if (a != hipSuccess) return a;
         attr_set = true;
     }
-    const size_t lds = MfmaLds<T, NB, HERM>::bytes(single.t.N, single.t.W, single.t.D);
-    hipLaunchKernelGGL((k_bulk_mfma<T, NB, HERM, BATCHED, NBASE>), dim3(total_tiles),
-                       dim3(128 * NB), lds, stream, single, jobs_dev, n_jobs, sp);
+    constexpr int AW = mfma_ados_per_wg<T, NB>();
+    const unsigned stride =
+        (unsigned)((MfmaLds<T, NB, HERM>::bytes(single.t.N, single.t.W, single.t.D) + 15) & ~(size_t)15);
+    hipLaunchKernelGGL((k_bulk_mfma<T, NB, HERM, BATCHED, NBASE>), dim3((total_tiles + AW - 1) / AW),
+                       dim3(128 * NB * AW), (size_t)stride * AW, stream, single, jobs_dev, n_jobs, sp,
+                       total_tiles, stride);
     return hipGetLastError();
 }
 
