@@ -105,7 +105,10 @@ def _replay(heom, reqs, precision, max_active, arena_bytes, rate, timeout_s=600.
     t0 = time.monotonic()
     arrival = 0.0
     tickets = []
-    for r in reqs:
+    for k, r in enumerate(reqs):
+        if rate is not None and (k + 1) % 16 == 0:
+            print("  submitted %d/%d, %.1f s" % (k + 1, len(reqs), time.monotonic() - t0),
+                  file=sys.stderr, flush=True)
         if rate is not None:
             arrival += r["gap"] / rate
             delay = t0 + arrival - time.monotonic()
@@ -114,8 +117,11 @@ def _replay(heom, reqs, precision, max_active, arena_bytes, rate, timeout_s=600.
         tickets.append(srv.submit(r["runs"], precision))
     lat, work = [], 0
     t_end = t0
-    for r, t in zip(reqs, tickets):
+    for k, (r, t) in enumerate(zip(reqs, tickets)):
         res = srv.wait(t, timeout_s)
+        if (k + 1) % 16 == 0 or k + 1 == len(reqs):
+            print("  %d/%d requests done, %.1f s" % (k + 1, len(reqs), time.monotonic() - t0),
+                  file=sys.stderr, flush=True)
         if res["status"] != 0:
             raise RuntimeError("request %d failed: %s" % (r["id"], res["status"]))
         lat.append(res["t_finish"] - res["t_submit"])
@@ -148,7 +154,9 @@ def run_serve(args):
     print("serve: %d requests, capacity %.2f req/s (%.1f s closed loop), replay at %.2f req/s"
           % (len(reqs), capacity, span_c, rate), file=sys.stderr, flush=True)
     # 2. the same Poisson trace through the batched server and through FP64 one-at-a-time
+    print("serve: batched FP32-mixed replay", file=sys.stderr, flush=True)
     lat_b, span_b, work_b = _replay(heom, reqs, heom.FP32_MIXED, args.serve_slots, arena, rate)
+    print("serve: plain FP64 one-at-a-time replay", file=sys.stderr, flush=True)
     lat_f, span_f, work_f = _replay(heom, reqs, heom.FP64, 1, arena, rate)
     line = {
         "metric": METRIC,
