@@ -67,7 +67,7 @@ struct Derived {
 
 // Table layout inside the caller's tables buffer.
 struct Layout {
-    size_t h_re, h_im, mode_site, mode_gamma, mode_c, mode_lamnu, plus_coef, minus_coef,
+    size_t h_re, h_im, h_re_f32, mode_site, mode_gamma, mode_c, mode_lamnu, plus_coef, minus_coef,
         delta_state, state_mode_begin, state_modes, binom, consts_end;
     size_t tuples, level, plus, minus, mlist, mlist_site, mlist_w, plus_w, damping, total;
 };
@@ -84,6 +84,7 @@ Layout make_layout(int N, int W, int D, int64_t n_ado) {
     const size_t WD = (size_t)W * (D + 1);
     L.h_re = take(NN * 8);
     L.h_im = take(NN * 8);
+    L.h_re_f32 = take(NN * 4);
     L.mode_site = take(W * 4);
     L.mode_gamma = take(W * 8);
     L.mode_c = take(W * 8);
@@ -391,6 +392,8 @@ heom_status heom_build_hierarchy(const heom_problem* problem, void* tables_dev,
     const size_t NN = (size_t)D.N * D.N;
     put(L.h_re, D.h_re.data(), NN * 8);
     put(L.h_im, D.h_im.data(), NN * 8);
+    std::vector<float> h32(D.h_re.begin(), D.h_re.end());
+    put(L.h_re_f32, h32.data(), NN * 4);
     put(L.mode_site, D.mode_site.data(), D.W * 4);
     put(L.mode_gamma, D.mode_gamma.data(), D.W * 8);
     put(L.mode_c, D.mode_c.data(), D.W * 8);
@@ -411,6 +414,7 @@ heom_status heom_build_hierarchy(const heom_problem* problem, void* tables_dev,
     t.h_complex = D.h_complex ? 1 : 0;
     t.h_re = reinterpret_cast<const double*>(base + L.h_re);
     t.h_im = reinterpret_cast<const double*>(base + L.h_im);
+    t.h_re_f32 = reinterpret_cast<const float*>(base + L.h_re_f32);
     t.mode_site = reinterpret_cast<const int32_t*>(base + L.mode_site);
     t.mode_gamma = reinterpret_cast<const double*>(base + L.mode_gamma);
     t.mode_c = reinterpret_cast<const double*>(base + L.mode_c);

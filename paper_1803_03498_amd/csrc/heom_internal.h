@@ -20,6 +20,7 @@ struct Tables {
     int32_t h_complex;            // H has a non-zero imaginary part
     const double* h_re;           // [N*N] rad/fs, diagonal shifted by -mean(diag)
     const double* h_im;           // [N*N]
+    const float* h_re_f32;        // [N*N] h_re rounded to FP32 (FP32 stage kernels)
     const int32_t* mode_site;     // [W]
     const double* mode_gamma;     // [W] 1/fs
     const double* mode_c;         // [W] rad/fs^2 (times the gauge sign)

@@ -646,6 +646,15 @@ __device__ __forceinline__ int mfma_row<double>(int lane, int r) {
 constexpr int kPrefRows = 4;
 
 // LDS carve-up of the MFMA stage kernel (bytes; T-typed arrays first).
+// H (shifted, rad/fs) in the stage precision: FP32 kernels read the FP32 copy.
+template <typename T>
+__device__ __forceinline__ T h_entry(const Tables& t, int idx) {
+    if constexpr (sizeof(T) == 4)
+        return G(t.h_re_f32)[idx];
+    else
+        return G(t.h_re)[idx];
+}
+
 template <typename T, int NB, bool HERM>
 struct MfmaLds {
     static constexpr int NP = 16 * NB;
@@ -780,17 +789,26 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute
     const bool jin = active && j < N;  // this thread's column is stored
 
     // 1. Independent loads: this ADO's tile, its link tables, this wave's block of H.
+    // Own elements: clamped, unpredicated loads (they issue together), then
+    // zeroed outside the N x N block by a multiply that cannot become a branch.
     C cur[EPT];
+    const int jc = min(j, N - 1);
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
         const int i = r0 + RS * k;
-        cur[k] = (jin && i < N) ? ld<T>(own, i * N + j) : C{(T)0, (T)0};
+        const T m = (jin && i < N) ? (T)1 : (T)0;
+        cur[k] = ld<T>(own, min(i, N - 1) * N + jc);
+        cur[k].re *= m;
+        cur[k].im *= m;
     }
     T hreg[KS];  // A operand: H[16 mt + lane%16][4 ks + lane/16]
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-        const int r = 16 * mt + (lane & 15), c = 4 * ks + (lane >> 4);
-        hreg[ks] = (r < N && c < N) ? (T)G(t.h_re)[r * N + c] : (T)0;
+        // Clamped and unpredicated, so the loads issue together: columns
+        // past N meet the zero rows of the padded sigma planes, and rows
+        // past N of X are never read.
+        const int r = min(16 * mt + (lane & 15), N - 1), c = min(4 * ks + (lane >> 4), N - 1);
+        hreg[ks] = h_entry<T>(t, r * N + c);
     }
     const int lev = G(t.level)[u];
     const T gam = (T)G(t.damping)[u];
@@ -879,8 +897,10 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute
             acc_t acc = {0, 0, 0, 0};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
-                const int kr = 4 * ks + (lane >> 4), jc = 16 * cb + (lane & 15);
-                const T hb = (kr < N && jc < N) ? (T)G(t.h_re)[kr * N + jc] : (T)0;
+                // clamped as for X: rows past N meet zero columns of S,
+                // columns past N of Y are never read
+                const int kr = min(4 * ks + (lane >> 4), N - 1), hc = min(16 * cb + (lane & 15), N - 1);
+                const T hb = h_entry<T>(t, kr * N + hc);
                 const T av = plane[(rb + (lane & 15)) * LS + 4 * ks + (lane >> 4)];
                 acc = mfma16(av, hb, acc);
             }
@@ -995,7 +1015,7 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute
 #pragma unroll
             for (int k = 0; k < EPT; ++k) {
                 const int i = r0 + RS * k;
-                bv[m][k] = (jin && i < N) ? ld<T>(bp, i * N + j) : C{(T)0, (T)0};
+                bv[m][k] = ld<T>(bp, min(i, N - 1) * N + jc);  // unused outside N x N
             }
         }
     }
