@@ -839,52 +839,36 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute
     }
     __syncthreads();
 
-    // 2. In flight during the matrix cores: the "-" neighbour rows
-    //    (Hermitian path) and the "+" neighbour values of this thread's elements.
+    // 2. In flight during the matrix cores: the "-" neighbour rows (Hermitian path).
     C pre = {(T)0, (T)0};
     const bool has_pre = HERM && tid < n_rows * N && sMnb[tid / N] >= 0;
     if (has_pre) {
         const int a = tid / N, c = tid - (tid / N) * N;
         pre = load_nb<T>(nbs, sMnb[a], sMsite[a], c);
     }
-    C xp[EPT][KX];
-#pragma unroll
-    for (int k = 0; k < EPT; ++k)
-#pragma unroll
-        for (int q = 0; q < KX; ++q) xp[k][q] = {(T)0, (T)0};
-    if (has_plus && jin) {
-#pragma unroll
-        for (int k = 0; k < EPT; ++k) {
-            const int i = r0 + RS * k;
-            if (i < N && i != j) {
-#pragma unroll
-                for (int q = 0; q < KX; ++q) {
-                    // Hermitian: modes of state i; general: modes of state i,
-                    // then of state j; all at (i, j)
-                    const int s = (q < KP) ? i : j, qq = (q < KP) ? q : q - KP;
-                    const int m0 = sBegin[s];
-                    if (qq < sBegin[s + 1] - m0) xp[k][q] = ld<T>(sPptr[sModes[m0 + qq]], i * N + j);
-                }
-            }
-        }
-    }
-
-    // 3. X = H [Re S | Im S]: this wave's 16-row block against every column block.
+    // 3. X = H [Re S | Im S]: this wave's 16-row block against every column
+    //    block, the NB accumulator chains interleaved so that their LDS reads
+    //    and matrix-core latencies overlap.
     {
         const T* plane = half ? sSim : sSre;
         T* out = half ? sXim : sXre;
+        acc_t acc[NB];
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb) {
-            acc_t acc = {0, 0, 0, 0};
+        for (int cb = 0; cb < NB; ++cb) acc[cb] = acc_t{0, 0, 0, 0};
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const T bval = plane[(4 * ks + (lane >> 4)) * LS + 16 * cb + (lane & 15)];
-                acc = mfma16(hreg[ks], bval, acc);
-            }
+        for (int ks = 0; ks < KS; ++ks) {
+            T bval[NB];
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb)
+                bval[cb] = plane[(4 * ks + (lane >> 4)) * LS + 16 * cb + (lane & 15)];
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb) acc[cb] = mfma16(hreg[ks], bval[cb], acc[cb]);
+        }
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                out[(16 * mt + mfma_row<T>(lane, r)) * LX + 16 * cb + (lane & 15)] = acc[r];
-        }
+                out[(16 * mt + mfma_row<T>(lane, r)) * LX + 16 * cb + (lane & 15)] = acc[cb][r];
     }
     if (!HERM) {
         // Y = S H: wave w takes row block w of [Re S; Im S]; H (real
@@ -914,6 +898,30 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute
         sRow[2 * tid + 1] = pre.im;
     }
     __syncthreads();  // sigma planes are free from here on
+
+    // The "+" neighbour values of this thread's elements.
+    C xp[EPT][KX];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k)
+#pragma unroll
+        for (int q = 0; q < KX; ++q) xp[k][q] = {(T)0, (T)0};
+    if (has_plus && jin) {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int i = r0 + RS * k;
+            if (i < N && i != j) {
+#pragma unroll
+                for (int q = 0; q < KX; ++q) {
+                    // Hermitian: modes of state i; general: modes of state i,
+                    // then of state j; all at (i, j)
+                    const int s = (q < KP) ? i : j, qq = (q < KP) ? q : q - KP;
+                    const int m0 = sBegin[s];
+                    if (qq < sBegin[s + 1] - m0) xp[k][q] = ld<T>(sPptr[sModes[m0 + qq]], i * N + j);
+                }
+            }
+        }
+    }
+
 
     // 4. Coupling sums Z into the sigma planes; the stage bases in flight.
     //    The first kPrefRows "-" links are wave-uniform (scalar registers);
