@@ -38,6 +38,34 @@ WORKLOADS = {
 }
 
 
+def _kernel_source_digest():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1803_03498_amd", "csrc", "heom_kernels.hip")
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel, workload, precision):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when there is none or
+    the kernel source has changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_%s_traffic.txt" % (kernel, workload, precision))
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != _kernel_source_digest():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -272,8 +300,9 @@ def main():
     kbytes = ctypes.c_double()
     lib.heom_timing_read(ctypes.byref(ms), ctypes.byref(launches), ctypes.byref(kbytes), 1)
 
-    kernel_name = ("k_bulk_mfma" if info["bulk_kernel"] else "k_bulk_fma") + \
-        " (RK4 stage, ADOs u>=1)"
+    kernel_short = "k_bulk_mfma" if info["bulk_kernel"] else "k_bulk_fma"
+    kernel_name = kernel_short + " (RK4 stage, ADOs u>=1)"
+    traffic = measured_traffic(kernel_short, args.workload, args.precision)
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / steps
     ado_updates = n * steps / elapsed
@@ -324,7 +353,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
             "avg_launch_ms": avg_launch_s * 1e3,
             "bytes_per_launch_algorithmic": bytes_per_launch,
         },
