@@ -35,7 +35,21 @@ WORKLOADS = {
     "aggregate24": lambda: hi.aggregate24(),
     "fmo_like": lambda: hi.fmo_like(),
     "dimer": lambda: hi.dimer(),
+    # the largest request of the serving mix as a single propagation
+    # (14 sites, W = 28, depth 5: 237336 ADOs of 14x14, FMA kernel)
+    "mix_largest": lambda: _mix_largest(),
 }
+
+
+def _mix_largest():
+    from math import comb
+    reqs = hi.serving_mix(n_requests=128, seed=512, n_steps=200)
+    def size(r):
+        W = sum(b["matsubara"] + 1 for b in r["runs"][0]["baths"])
+        return comb(W + r["depth"], W) * r["N"] ** 2
+    run = dict(max(reqs, key=size)["runs"][0])
+    run["record_every"] = 10
+    return run
 
 
 def _kernel_source_digest():

@@ -490,6 +490,7 @@ TimingState g_timing;
 heom::Job base_job(const heom_hierarchy* h) {
     heom::Job j{};
     j.t = h->t;
+    j.any_complex_h = h->t.h_complex;
     j.dt = 1.0;
     j.tile_begin = 0;
     j.ados_per_tile =

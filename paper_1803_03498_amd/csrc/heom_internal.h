@@ -12,6 +12,7 @@ namespace heom {
 
 constexpr int kMaxStates = 64;
 constexpr int kBlock = 256;
+constexpr int kFmaBlock = 256;  // threads of an FMA-path stage workgroup
 
 // Device pointers into the caller's tables buffer, plus the scalars the
 // kernels need.  Everything here is written once by heom_build_hierarchy.
@@ -55,6 +56,7 @@ struct Job {
     int32_t n_tiles;              // bulk tiles of this job
     int32_t ados_per_tile;
     uint32_t lds_bytes;           // batched launches: LDS of the largest tile (0 = derive)
+    int32_t any_complex_h;        // some job of the launch has a complex H
     double* records;              // [n_rec_max][rec_doubles]
     const double* mu;             // [N] (dipole observable)
     int64_t* step;                // device step counter
@@ -105,7 +107,7 @@ __host__ __device__ inline FmaLds fma_lds(int N, int W, int D, int GA, int tsize
     return L;
 }
 
-// ADOs per FMA-path tile: 256 / N^2 threads' worth, reduced to fit 64 KiB of LDS.
+// ADOs per FMA-path tile: kFmaBlock / N^2 threads' worth, reduced to fit 64 KiB of LDS.
 int bulk_ados_per_tile(int N, int W, int D, int tsize);
 // Name of the kernel whose launch failed in the last launch_stage call on this thread.
 const char* last_launch_failure();

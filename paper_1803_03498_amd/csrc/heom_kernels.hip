@@ -445,16 +445,34 @@ __global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int
     }
 }
 
+// H (shifted, rad/fs) in the stage precision: FP32 kernels read the FP32 copy.
+template <typename T>
+__device__ __forceinline__ T h_entry(const Tables& t, int idx) {
+    if constexpr (sizeof(T) == 4)
+        return G(t.h_re_f32)[idx];
+    else
+        return G(t.h_re)[idx];
+}
+
+// At most this many "-" links of an ADO are read ahead by the stage kernels
+// (the MFMA kernel stages their neighbour rows in LDS); further links read
+// global memory where they are used.
+constexpr int kPrefRows = 4;
+
 // --------------------------------------------------------------------------
 // Bulk stage kernel, wavefront-FMA path (N < 16, or complex H): a workgroup
-// takes GA = max(1, 256 / N^2) consecutive ADOs; every thread owns whole
-// matrix elements.  Each ADO's links are staged in LDS first (the compact
-// "-" list, and the "+" row when its level is below D), so an element's
-// coupling lines need one global load per contributing neighbour.
+// of kFmaBlock threads takes GA = max(1, kFmaBlock / N^2) consecutive ADOs;
+// every thread owns whole matrix elements.  Each ADO's link rows (the
+// compact "-" list with its states and weights, the "+" neighbours and
+// weights) are copied to LDS first from the precomputed tables, so an
+// element's coupling lines need one global load per contributing neighbour.
+// The kernel is kept lean in registers: at this size the number of resident
+// workgroups, not the order of the loads, decides the throughput.
+// HC: some job of the launch has a complex H (otherwise H is real).
 // --------------------------------------------------------------------------
-template <typename T, bool BATCHED>
-__global__ __launch_bounds__(256) void k_bulk_fma(Job single, const Job* jobs, int n_jobs,
-                                                  StageSpec sp) {
+template <typename T, bool BATCHED, bool HC>
+__global__ __launch_bounds__(kFmaBlock) void k_bulk_fma(Job single, const Job* jobs, int n_jobs,
+                                                        StageSpec sp) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const Job& J = JobOf<BATCHED>::get(single, jobs, n_jobs, b);
     const Tables& t = J.t;
@@ -481,7 +499,7 @@ __global__ __launch_bounds__(256) void k_bulk_fma(Job single, const Job* jobs, i
 
     // stage H, the tile, the per-ADO link data and the per-state tables
     for (int e = tid; e < NN; e += blockDim.x) {
-        sH[2 * e] = (T)G(t.h_re)[e];
+        sH[2 * e] = h_entry<T>(t, e);
         sH[2 * e + 1] = t.h_complex ? (T)G(t.h_im)[e] : (T)0;
     }
     const size_t base = (size_t)(u0 - 1) * NN;
@@ -495,31 +513,21 @@ __global__ __launch_bounds__(256) void k_bulk_fma(Job single, const Job* jobs, i
         }
     }
     for (int x = tid; x < n_here * Dm; x += blockDim.x) {
-        const int g = x / Dm, a = x - g * Dm;
-        const pair_i ml = G(reinterpret_cast<const pair_i*>(t.mlist))[(size_t)(u0 + g) * Dm + a];
-        sMnb[x] = ml.x;
-        if (ml.x >= 0) {
-            const int mode = ml.y & 255, nl = ml.y >> 8;
-            const double coef = G(t.minus_coef)[mode * (D + 1) + nl];
-            sMsite[x] = G(t.mode_site)[mode];
-            sMml[x] = (T)(coef * G(t.mode_lamnu)[mode]);
-            sMmc[x] = (T)(coef * G(t.mode_c)[mode]);
-        } else {
-            sMsite[x] = -1;
-        }
+        const size_t at = (size_t)u0 * Dm + x;  // row u0 + x / Dm, entry x % Dm
+        const pair_d w = G(reinterpret_cast<const pair_d*>(t.mlist_w))[at];
+        sMnb[x] = G(reinterpret_cast<const pair_i*>(t.mlist))[at].x;
+        sMsite[x] = G(t.mlist_site)[at];
+        sMml[x] = (T)w.x;
+        sMmc[x] = (T)w.y;
     }
     for (int g = tid; g < n_here; g += blockDim.x) {
         sLev[g] = G(t.level)[u0 + g];
         sGam[g] = (T)G(t.damping)[u0 + g];
     }
     for (int x = tid; x < n_here * W; x += blockDim.x) {
-        const int g = x / W, l = x - g * W;
-        const int u = u0 + g;
-        if (G(t.level)[u] < D) {
-            const int nl = G(t.tuples)[(size_t)u * W + l];
-            sPnb[x] = G(t.plus)[(size_t)u * W + l];
-            sPa[x] = (T)G(t.plus_coef)[l * (D + 1) + nl];
-        }
+        const size_t at = (size_t)u0 * W + x;
+        sPnb[x] = G(t.plus)[at];
+        sPa[x] = (T)G(t.plus_w)[at];
     }
     for (int x = tid; x <= N; x += blockDim.x) {
         sBegin[x] = G(t.state_mode_begin)[x];
@@ -529,7 +537,7 @@ __global__ __launch_bounds__(256) void k_bulk_fma(Job single, const Job* jobs, i
     __syncthreads();
 
     const NbSrc<T> nbs{J.sig0[sp.in], J.rest[sp.in], N};
-    const bool herm = J.herm != 0, hc = t.h_complex != 0;
+    const bool herm = J.herm != 0, hc = HC && t.h_complex != 0;
     const T h = (T)(sp.hmul * J.dt), w_in = (T)sp.w_in;
     for (int e = tid; e < tot; e += blockDim.x) {
         const int g = e / NN;
@@ -641,20 +649,8 @@ __device__ __forceinline__ int mfma_row<double>(int lane, int r) {
     return 4 * r + (lane >> 4);
 }
 
-// At most this many "-" neighbour rows are prefetched into LDS per ADO
-// (one element per thread); further links read global memory directly.
-constexpr int kPrefRows = 4;
 
 // LDS carve-up of the MFMA stage kernel (bytes; T-typed arrays first).
-// H (shifted, rad/fs) in the stage precision: FP32 kernels read the FP32 copy.
-template <typename T>
-__device__ __forceinline__ T h_entry(const Tables& t, int idx) {
-    if constexpr (sizeof(T) == 4)
-        return G(t.h_re_f32)[idx];
-    else
-        return G(t.h_re)[idx];
-}
-
 template <typename T, int NB, bool HERM>
 struct MfmaLds {
     static constexpr int NP = 16 * NB;
@@ -1077,7 +1073,7 @@ int bulk_mfma_blocks(int N, bool h_complex, int precision) {
 
 int bulk_ados_per_tile(int N, int W, int D, int tsize) {
     const int NN = N * N;
-    int g = NN >= kBlock ? 1 : kBlock / NN;
+    int g = NN >= kFmaBlock ? 1 : kFmaBlock / NN;
     // keep a tile's LDS (matrices plus staged links) within 64 KiB
     while (g > 1 && fma_lds(N, W, D, g, tsize).total > 64 * 1024) --g;
     return g;
@@ -1175,18 +1171,18 @@ static hipError_t launch_sigma0_t(const Job& single, const Job* jobs_dev, int n_
     return hipGetLastError();
 }
 
-template <typename T, bool BATCHED>
+template <typename T, bool BATCHED, bool HC>
 static hipError_t launch_fma_t(const Job& single, const Job* jobs_dev, int n_jobs,
                                int total_tiles, const StageSpec& sp, size_t lds,
                                hipStream_t stream) {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bulk_fma<T, BATCHED>),
+        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bulk_fma<T, BATCHED, HC>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (a != hipSuccess) return a;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_bulk_fma<T, BATCHED>), dim3(total_tiles), dim3(kBlock), lds, stream,
+    hipLaunchKernelGGL((k_bulk_fma<T, BATCHED, HC>), dim3(total_tiles), dim3(kFmaBlock), lds, stream,
                        single, jobs_dev, n_jobs, sp);
     return hipGetLastError();
 }
@@ -1218,8 +1214,12 @@ static hipError_t launch_stage_t(const Job& single, const Job* jobs_dev, int n_j
                                ? (size_t)single.lds_bytes
                                : fma_lds(N, single.t.W, single.t.D, single.ados_per_tile,
                                          (int)sizeof(T)).total;
-        e = batched ? launch_fma_t<T, true>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream)
-                    : launch_fma_t<T, false>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream);
+        if (single.any_complex_h)
+            e = batched ? launch_fma_t<T, true, true>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream)
+                        : launch_fma_t<T, false, true>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream);
+        else
+            e = batched ? launch_fma_t<T, true, false>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream)
+                        : launch_fma_t<T, false, false>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream);
         if (e != hipSuccess) g_launch_what = "FMA bulk stage kernel";
     }
     if (e != hipSuccess) return e;

@@ -311,9 +311,10 @@ bool heom_server::rebuild() {
         g.job_off = off;
         g.n_jobs = (int)kv.second.size();
         g.sizing = *kv.second.front();
-        int maxN = 0, maxW = 0, maxD = 0, tiles = 0;
+        int maxN = 0, maxW = 0, maxD = 0, tiles = 0, any_hc = 0;
         size_t fma_bytes = 0;
         for (const heom::Job* j : kv.second) {
+            any_hc |= j->t.h_complex != 0;
             if (g.nb == 0)
                 fma_bytes = std::max(fma_bytes, heom::fma_lds(j->t.N, j->t.W, j->t.D, j->ados_per_tile,
                                                               g.precision == HEOM_FP64 ? 8 : 4).total);
@@ -332,6 +333,7 @@ bool heom_server::rebuild() {
         g.sizing.t.D = maxD;
         g.sizing.herm = g.herm;
         g.sizing.lds_bytes = (uint32_t)fma_bytes;
+        g.sizing.any_complex_h = any_hc;
         if (g.nb == 0) g.sizing.t.h_complex = 1;  // selects the FMA path for any N
         groups.push_back(g);
     }
