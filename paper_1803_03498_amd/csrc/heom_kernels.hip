@@ -471,8 +471,8 @@ constexpr int kPrefRows = 4;
 // HC: some job of the launch has a complex H (otherwise H is real).
 // --------------------------------------------------------------------------
 template <typename T, bool BATCHED, bool HC>
-__global__ __launch_bounds__(kFmaBlock) void k_bulk_fma(Job single, const Job* jobs, int n_jobs,
-                                                        StageSpec sp) {
+__global__ __launch_bounds__(kFmaBlock) __attribute__((amdgpu_waves_per_eu(
+    sizeof(T) == 4 ? 8 : 5))) void k_bulk_fma(Job single, const Job* jobs, int n_jobs, StageSpec sp) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const Job& J = JobOf<BATCHED>::get(single, jobs, n_jobs, b);
     const Tables& t = J.t;
@@ -534,6 +534,14 @@ __global__ __launch_bounds__(kFmaBlock) void k_bulk_fma(Job single, const Job* j
         if (x < N) sDelta[x] = (T)G(t.delta_state)[x];
     }
     for (int l = tid; l < W; l += blockDim.x) sModes[l] = G(t.state_modes)[l];
+    // FP32: this thread's first stage-base elements, in flight across the
+    // barrier (FP64 keeps the registers for occupancy and loads them late)
+    constexpr bool kEarly = sizeof(T) == 4;
+    cpx<T> bv0[3];
+    const int e0c = min((int)tid, tot - 1);
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+        if (kEarly && m < sp.nbase) bv0[m] = ld<T>(J.rest[sp.base[m]], base + e0c);
     __syncthreads();
 
     const NbSrc<T> nbs{J.sig0[sp.in], J.rest[sp.in], N};
@@ -592,10 +600,13 @@ __global__ __launch_bounds__(kFmaBlock) void k_bulk_fma(Job single, const Job* j
             }
         }
         T yr = w_in * sr + h * fr, yi = w_in * si + h * fi;
-        for (int m = 0; m < sp.nbase; ++m) {
-            const cpx<T> bv = ld<T>(J.rest[sp.base[m]], base + e);
-            yr += (T)sp.wbase[m] * bv.re;
-            yi += (T)sp.wbase[m] * bv.im;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            if (m < sp.nbase) {
+                const cpx<T> bv = (kEarly && e == (int)tid) ? bv0[m] : ld<T>(J.rest[sp.base[m]], base + e);
+                yr += (T)sp.wbase[m] * bv.re;
+                yi += (T)sp.wbase[m] * bv.im;
+            }
         }
         st<T>(J.rest[sp.out], base + e, cpx<T>{yr, yi});
     }
