@@ -88,7 +88,18 @@ RHS_CASES = [
     (18, 5, 5, 1, 2, {"flags": 4}),
     (19, 5, 5, 1, 2, {"flags": 8}),
     (20, 4, 6, 1, 2, {}),       # several baths on one state
+    # matrix-core path corner cases: an odd number of bulk tiles (two ADOs
+    # per FP32 workgroup leave one half idle), three modes per state (more
+    # "+" modes than are loaded ahead), depth 5 (more "-" links than are
+    # staged as rows)
+    (21, 40, 39, 0, 1, {}),
+    (22, 44, 17, 1, 2, {}),
+    (23, 40, 10, 2, 2, {}),
+    (24, 20, 3, 1, 5, {}),
+    (25, 40, 3, 1, 5, {}),
+    (26, 14, 14, 1, 3, {}),     # the serving mix's largest N on the FMA path
 ]
+FP32_CASES = RHS_CASES[:14] + RHS_CASES[20:]
 
 
 def _rhs_problem(seed, N, nb, M, D, extra):
@@ -114,17 +125,19 @@ def test_rhs_fp64(heom, orc, case, herm):
     assert err <= 1e-12 * np.max(np.abs(ref)), err
 
 
-@pytest.mark.parametrize("case", RHS_CASES[:14], ids=[f"N{c[1]}" for c in RHS_CASES[:14]])
-def test_rhs_fp32_mixed(heom, orc, case):
+@pytest.mark.parametrize("case", FP32_CASES, ids=[f"N{c[1]}_B{c[2]}_M{c[3]}_D{c[4]}_{c[0]}"
+                                                  for c in FP32_CASES])
+@pytest.mark.parametrize("herm", [True, False])
+def test_rhs_fp32_mixed(heom, orc, case, herm):
     seed, N, nb, M, D, extra = case
-    _print_case("rhs fp32", case)
+    _print_case("rhs fp32", case, herm)
     prob = _rhs_problem(seed, N, nb, M, D, extra)
     h = heom.Hierarchy(prob, heom.FP32_MIXED)
-    x = hi.random_state(200 + seed, h.n_ado, N, hermitian=True)
+    x = hi.random_state(200 + seed, h.n_ado, N, hermitian=herm)
     x[1:] = x[1:].astype(np.complex64)  # the oracle sees the same FP32 inputs
     ref = orc.rhs(prob, x)
     out = h.new_state()
-    h.rhs(h.state_from_numpy(x), out, hermitian=True)
+    h.rhs(h.state_from_numpy(x), out, hermitian=herm)
     got = h.state_to_numpy(out)
     scale = np.max(np.abs(ref))
     assert np.max(np.abs(got[0] - ref[0])) <= 1e-6 * scale  # sigma_0 row: FP64 arithmetic
