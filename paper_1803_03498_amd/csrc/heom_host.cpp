@@ -69,7 +69,7 @@ struct Derived {
 struct Layout {
     size_t h_re, h_im, h_re_f32, mode_site, mode_gamma, mode_c, mode_lamnu, plus_coef, minus_coef,
         delta_state, state_mode_begin, state_modes, binom, consts_end;
-    size_t tuples, level, plus, minus, mlist, mlist_site, mlist_w, plus_w, damping, total;
+    size_t tuples, level, plus, minus, mlist, mlist_site, mlist_w, mlist_w32, plus_w, damping, total;
 };
 
 Layout make_layout(int N, int W, int D, int64_t n_ado) {
@@ -103,6 +103,7 @@ Layout make_layout(int N, int W, int D, int64_t n_ado) {
     L.mlist = take((size_t)n_ado * std::max(D, 1) * 8);
     L.mlist_site = take((size_t)n_ado * std::max(D, 1) * 4);
     L.mlist_w = take((size_t)n_ado * std::max(D, 1) * 16);
+    L.mlist_w32 = take((size_t)n_ado * std::max(D, 1) * 8);
     L.plus_w = take((size_t)n_ado * W * 8);
     L.damping = take((size_t)n_ado * 8);
     L.total = o;
@@ -432,6 +433,7 @@ heom_status heom_build_hierarchy(const heom_problem* problem, void* tables_dev,
     t.mlist = reinterpret_cast<int32_t*>(base + L.mlist);
     t.mlist_site = reinterpret_cast<int32_t*>(base + L.mlist_site);
     t.mlist_w = reinterpret_cast<double*>(base + L.mlist_w);
+    t.mlist_w32 = reinterpret_cast<float*>(base + L.mlist_w32);
     t.plus_w = reinterpret_cast<double*>(base + L.plus_w);
     t.damping = reinterpret_cast<double*>(base + L.damping);
 

@@ -40,6 +40,7 @@ struct Tables {
                                   // [0] = neighbour (-1 = none), [1] = mode | n_l << 8
     int32_t* mlist_site;          // [n_ado][max(D,1)]: state of each "-" link (-1 = none)
     double* mlist_w;              // [n_ado][max(D,1)][2]: sqrt(n_l/|c_l|) * (lambda nu, c_l)
+    float* mlist_w32;             // the same rounded to FP32 (FP32 stage kernels)
     double* plus_w;               // [n_ado][W]: sign * sqrt((n_l+1)|c_l|), 0 = absent
     double* damping;              // [n_ado]: sum_l n_l gamma_l
 };

@@ -147,6 +147,7 @@ __global__ __launch_bounds__(256) void k_minus_list(Tables t) {
     gptr<pair_i> out = G(reinterpret_cast<pair_i*>(t.mlist)) + (size_t)u * Dm;
     gptr<int32_t> site = G(t.mlist_site) + (size_t)u * Dm;
     gptr<pair_d> wt = G(reinterpret_cast<pair_d*>(t.mlist_w)) + (size_t)u * Dm;
+    gptr<pair_f> wt32 = G(reinterpret_cast<pair_f*>(t.mlist_w32)) + (size_t)u * Dm;
     int k = 0;
     for (int l = 0; l < W && k < Dm; ++l) {
         const int nl = G(t.tuples)[(size_t)u * W + l];
@@ -160,6 +161,10 @@ __global__ __launch_bounds__(256) void k_minus_list(Tables t) {
             w.y = b * G(t.mode_c)[l];
             site[k] = G(t.mode_site)[l];
             wt[k] = w;
+            pair_f w32;
+            w32.x = (float)w.x;
+            w32.y = (float)w.y;
+            wt32[k] = w32;
             out[k++] = v;
         }
     }
@@ -172,6 +177,10 @@ __global__ __launch_bounds__(256) void k_minus_list(Tables t) {
         w.y = 0.0;
         site[k] = -1;
         wt[k] = w;
+        pair_f w32;
+        w32.x = 0.0f;
+        w32.y = 0.0f;
+        wt32[k] = w32;
         out[k] = v;
     }
 }
@@ -820,6 +829,29 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute
     const int lev = G(t.level)[u];
     const T gam = (T)G(t.damping)[u];
     const bool has_plus = lev < D;
+    // The first kPrefRows "-" links as wave-uniform scalars, read from the
+    // tables at a uniform address (scalar loads, no LDS round trip).
+    int lsite[kPrefRows];
+    T lml[kPrefRows], lmc[kPrefRows];
+#pragma unroll
+    for (int a = 0; a < kPrefRows; ++a) {
+        const size_t at = (size_t)u * Dm + min(a, Dm - 1);
+        lsite[a] = a < Dm ? G(t.mlist_site)[at] : -1;
+        if constexpr (sizeof(T) == 4) {
+            const pair_f w = G(reinterpret_cast<const pair_f*>(t.mlist_w32))[at];
+            lml[a] = w.x;
+            lmc[a] = w.y;
+        } else {
+            const pair_d w = G(reinterpret_cast<const pair_d*>(t.mlist_w))[at];
+            lml[a] = w.x;
+            lmc[a] = w.y;
+        }
+    }
+    // the stage bases of this ADO
+    const char* bptr[NBASE];
+#pragma unroll
+    for (int m = 0; m < NBASE; ++m)
+        bptr[m] = reinterpret_cast<const char*>(J.rest[sp.base[m < sp.nbase ? m : 0]]) + (size_t)(u - 1) * tile_bytes;
     for (int a = tid; a < Dm; a += NT) {
         const pair_d w = G(reinterpret_cast<const pair_d*>(t.mlist_w))[(size_t)u * Dm + a];
         sMnb[a] = G(reinterpret_cast<const pair_i*>(t.mlist))[(size_t)u * Dm + a].x;
@@ -935,14 +967,6 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute
     //    mmask marks the states with a "-" link.
     T* sZre = sSre;
     T* sZim = sSim;
-    int lsite[kPrefRows];
-    T lml[kPrefRows], lmc[kPrefRows];
-#pragma unroll
-    for (int a = 0; a < kPrefRows; ++a) {
-        lsite[a] = uniform(a < Dm ? sMsite[a] : -1);
-        lml[a] = uniform(a < Dm ? sMml[a] : (T)0);
-        lmc[a] = uniform(a < Dm ? sMmc[a] : (T)0);
-    }
     uint64_t mmask = 0;
 #pragma unroll
     for (int a = 0; a < kPrefRows; ++a)
@@ -1018,19 +1042,21 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute
                 for (int a = kPrefRows; a < Dm; ++a)
                     if (sMsite[a] >= 0) minus(a, sMsite[a], sMml[a], sMmc[a]);
             }
-            sZre[i * LX + j] = zr;
-            sZim[i * LX + j] = zi;
+            // Z is stored only where it can be non-zero (read under the same test)
+            if (has_plus || row_i || row_j) {
+                sZre[i * LX + j] = zr;
+                sZim[i * LX + j] = zi;
+            }
         }
     }
     C bv[NBASE][EPT];
 #pragma unroll
     for (int m = 0; m < NBASE; ++m) {
         if (m < sp.nbase) {
-            const char* bp = reinterpret_cast<const char*>(J.rest[sp.base[m]]) + (size_t)(u - 1) * tile_bytes;
 #pragma unroll
             for (int k = 0; k < EPT; ++k) {
                 const int i = r0 + RS * k;
-                bv[m][k] = ld<T>(bp, min(i, N - 1) * N + jc);  // unused outside N x N
+                bv[m][k] = ld<T>(bptr[m], min(i, N - 1) * N + jc);  // unused outside N x N
             }
         }
     }
@@ -1048,16 +1074,26 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute
         if (i >= N) continue;
         const bool off = i != j;
         T cr, ci, zr, zi;
+        const bool zi_row = has_plus || ((mmask >> i) & 1), zj_row = has_plus || ((mmask >> j) & 1);
+        zr = zi = (T)0;
         if (HERM) {
             cr = sXre[i * LX + j] - sXre[j * LX + i];
             ci = sXim[i * LX + j] + sXim[j * LX + i];
-            zr = sZre[i * LX + j] + (off ? sZre[j * LX + i] : (T)0);
-            zi = sZim[i * LX + j] - (off ? sZim[j * LX + i] : (T)0);
+            if (zi_row) {
+                zr = sZre[i * LX + j];
+                zi = sZim[i * LX + j];
+            }
+            if (off && zj_row) {
+                zr += sZre[j * LX + i];
+                zi -= sZim[j * LX + i];
+            }
         } else {
             cr = sXre[i * LX + j] - sYre[i * LS + j];
             ci = sXim[i * LX + j] - sYim[i * LS + j];
-            zr = sZre[i * LX + j];
-            zi = sZim[i * LX + j];
+            if (zi_row || zj_row) {
+                zr = sZre[i * LX + j];
+                zi = sZim[i * LX + j];
+            }
         }
         const T sr = cur[k].re, si = cur[k].im;
         const T g = gam + (off ? sDelta[i] + dj : (T)0);
