@@ -324,15 +324,17 @@ __host__ __device__ inline Sigma0Lds sigma0_lds(int N, int W, int tsize, bool he
     return L;
 }
 
+// The sigma_0 stage of job `job` by the whole workgroup (any block size):
+// the body of k_sigma0, and of the extra workgroups of a bulk launch that
+// carries sigma_0 along (lds_cap: the LDS the launch provides).
 template <typename T, bool BATCHED>
-__global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int n_jobs,
-                                                StageSpec sp, unsigned lds_cap) {
-    const Job& J = BATCHED ? jobs[blockIdx.x] : single;
+__device__ void sigma0_stage(const Job& single, const Job* jobs, int job, const StageSpec& sp,
+                             unsigned lds_cap, char* smem_s0) {
+    const Job& J = BATCHED ? jobs[job] : single;
     const Tables& t = J.t;
     const int N = t.N, NN = N * N, W = t.W, D = t.D;
     const bool herm = J.herm != 0;
     const Sigma0Lds L = sigma0_lds(N, W, (int)sizeof(T), herm, lds_cap);
-    extern __shared__ char smem_s0[];
     double* sH = reinterpret_cast<double*>(smem_s0 + L.h);
     double* sS = reinterpret_cast<double*>(smem_s0 + L.s);
     double* sPa = reinterpret_cast<double*>(smem_s0 + L.pa);
@@ -454,6 +456,14 @@ __global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int
     }
 }
 
+template <typename T, bool BATCHED>
+__global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int n_jobs,
+                                                StageSpec sp, unsigned lds_cap) {
+    extern __shared__ char smem_s0[];
+    (void)n_jobs;
+    sigma0_stage<T, BATCHED>(single, jobs, blockIdx.x, sp, lds_cap, smem_s0);
+}
+
 // H (shifted, rad/fs) in the stage precision: FP32 kernels read the FP32 copy.
 template <typename T>
 __device__ __forceinline__ T h_entry(const Tables& t, int idx) {
@@ -481,8 +491,17 @@ constexpr int kPrefRows = 4;
 // --------------------------------------------------------------------------
 template <typename T, bool BATCHED, bool HC>
 __global__ __launch_bounds__(kFmaBlock) __attribute__((amdgpu_waves_per_eu(
-    sizeof(T) == 4 ? 8 : 5))) void k_bulk_fma(Job single, const Job* jobs, int n_jobs, StageSpec sp) {
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    sizeof(T) == 4 ? 8 : 5))) void k_bulk_fma(Job single, const Job* jobs, int n_jobs, StageSpec sp,
+                                              int s0_blocks, unsigned lds_total) {
+    extern __shared__ char smem_raw[];
+    if constexpr (sizeof(T) == 4) {
+        if ((int)blockIdx.x < s0_blocks) {
+            // the first workgroups carry the sigma_0 stage along
+            sigma0_stage<T, BATCHED>(single, jobs, blockIdx.x, sp, lds_total, smem_raw);
+            return;
+        }
+    }
+    const int b = xcd_remap(blockIdx.x - s0_blocks, gridDim.x - s0_blocks);
     const Job& J = JobOf<BATCHED>::get(single, jobs, n_jobs, b);
     const Tables& t = J.t;
     const int N = t.N, NN = N * N, W = t.W, D = t.D, Dm = D > 0 ? D : 1;
@@ -490,7 +509,6 @@ __global__ __launch_bounds__(kFmaBlock) __attribute__((amdgpu_waves_per_eu(
     const int u0 = 1 + (b - J.tile_begin) * GA;
     const int n_here = min(GA, t.n_ado - u0);
     const FmaLds L = fma_lds(N, W, D, GA, (int)sizeof(T));
-    extern __shared__ char smem_raw[];
     T* sH = reinterpret_cast<T*>(smem_raw + L.h);     // 2*NN
     T* sS = reinterpret_cast<T*>(smem_raw + L.s);     // 2*GA*NN
     T* sMml = reinterpret_cast<T*>(smem_raw + L.mw);  // [GA][Dm]
@@ -756,6 +774,7 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute
                                                                              unsigned lds_stride) {
     constexpr int NT = 128 * NB;  // threads per ADO
     constexpr int AW = mfma_ados_per_wg<T, NB>();
+    extern __shared__ char smem_raw[];
     using L = MfmaLds<T, NB, HERM>;
     constexpr int NP = L::NP, LS = L::LS, LX = L::LX, PLANE = L::PLANE, XPLANE = L::XPLANE;
     constexpr int KS = 4 * NB;      // k-steps of 4
@@ -783,7 +802,6 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute
     const NbSrc<T> nbs{J.sig0[sp.in], J.rest[sp.in], N};
     const int n_rows = L::n_rows(D);
 
-    extern __shared__ char smem_raw[];
     T* sSre = reinterpret_cast<T*>(smem_raw + (size_t)sub * lds_stride);  // sigma (stride LS), then Z (stride LX)
     T* sSim = sSre + PLANE;
     T* sXre = sSim + PLANE;  // stride LX
@@ -1140,6 +1158,45 @@ hipError_t launch_enumerate(const Tables& t, hipStream_t stream) {
     return hipGetLastError();
 }
 
+template <typename T, bool BATCHED>
+static hipError_t launch_sigma0_t(const Job& single, const Job* jobs_dev, int n_jobs,
+                                  const StageSpec& sp, size_t lds, hipStream_t stream) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sigma0<T, BATCHED>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (a != hipSuccess) return a;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_sigma0<T, BATCHED>), dim3(BATCHED ? n_jobs : 1), dim3(kBlock), lds,
+                       stream, single, jobs_dev, n_jobs, sp, (unsigned)lds);
+    return hipGetLastError();
+}
+
+// sigma_0 rides along with a bulk launch as n_s0 extra workgroups (placed
+// first) when the kernel carries it (`allow`) and its staging fits the
+// launch's LDS, which may grow up to `lds_budget` (what costs the bulk
+// kernel no occupancy); otherwise it gets its own launch first.  Sets the
+// number of workgroups to add and the launch's LDS.
+template <typename T, bool BATCHED>
+static hipError_t sigma0_ride_along(const Job& single, const Job* jobs_dev, int n_jobs, int n_s0,
+                                    bool allow, const StageSpec& sp, size_t lds_budget,
+                                    hipStream_t stream, int* added, size_t* lds) {
+    *added = 0;
+    const int N = single.t.N, W = single.t.W;
+    const size_t cap = std::max(*lds, lds_budget);
+    // largest N and W of the batch; non-Hermitian staging needs the most LDS
+    const size_t full = sigma0_lds(N, W, (int)sizeof(T), false, 160 * 1024).total;
+    const size_t bare = sigma0_lds(N, W, (int)sizeof(T), false, 0).total;
+    if (allow && (full <= cap || bare <= *lds)) {
+        if (full <= cap) *lds = std::max(*lds, full);
+        *added = n_s0;
+        return hipSuccess;
+    }
+    const size_t lds0 = sigma0_lds(N, W, (int)sizeof(T), false, 160 * 1024).total;
+    return launch_sigma0_t<T, BATCHED>(single, jobs_dev, n_jobs, sp, lds0, stream);
+}
+
 template <typename T, int NB, bool HERM, bool BATCHED, int NBASE>
 static hipError_t launch_mfma_t(const Job& single, const Job* jobs_dev, int n_jobs,
                                 int total_tiles, const StageSpec& sp, hipStream_t stream) {
@@ -1203,25 +1260,11 @@ static hipError_t launch_mfma(int nb, bool herm, const Job& single, const Job* j
     }
 }
 
-template <typename T, bool BATCHED>
-static hipError_t launch_sigma0_t(const Job& single, const Job* jobs_dev, int n_jobs,
-                                  const StageSpec& sp, size_t lds, hipStream_t stream) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sigma0<T, BATCHED>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (a != hipSuccess) return a;
-        attr_set = true;
-    }
-    hipLaunchKernelGGL((k_sigma0<T, BATCHED>), dim3(BATCHED ? n_jobs : 1), dim3(kBlock), lds,
-                       stream, single, jobs_dev, n_jobs, sp, (unsigned)lds);
-    return hipGetLastError();
-}
 
 template <typename T, bool BATCHED, bool HC>
 static hipError_t launch_fma_t(const Job& single, const Job* jobs_dev, int n_jobs,
                                int total_tiles, const StageSpec& sp, size_t lds,
-                               hipStream_t stream) {
+                               hipStream_t stream, int n_s0) {
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bulk_fma<T, BATCHED, HC>),
@@ -1229,8 +1272,15 @@ static hipError_t launch_fma_t(const Job& single, const Job* jobs_dev, int n_job
         if (a != hipSuccess) return a;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_bulk_fma<T, BATCHED, HC>), dim3(total_tiles), dim3(kFmaBlock), lds, stream,
-                       single, jobs_dev, n_jobs, sp);
+    // FP32 only: the FP64 sigma_0 code would cost the FP64 kernel its
+    // occupancy.  Eight FP32 workgroups per CU leave 20 KiB of LDS each.
+    int extra = 0;
+    size_t lds_launch = lds;
+    hipError_t e = sigma0_ride_along<T, BATCHED>(single, jobs_dev, n_jobs, n_s0, sizeof(T) == 4, sp,
+                                                 160 * 1024 / 8, stream, &extra, &lds_launch);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_bulk_fma<T, BATCHED, HC>), dim3(total_tiles + extra), dim3(kFmaBlock),
+                       lds_launch, stream, single, jobs_dev, n_jobs, sp, extra, (unsigned)lds_launch);
     return hipGetLastError();
 }
 
@@ -1242,31 +1292,45 @@ static hipError_t launch_stage_t(const Job& single, const Job* jobs_dev, int n_j
                                  hipEvent_t ev_begin, hipEvent_t ev_end) {
     const int N = single.t.N;
     const bool batched = jobs_dev != nullptr;
-    // sigma_0: largest N and W of the batch; non-Hermitian staging needs the most LDS
-    const size_t lds0 = sigma0_lds(N, single.t.W, (int)sizeof(T), false, 160 * 1024).total;
-    hipError_t e = batched ? launch_sigma0_t<T, true>(single, jobs_dev, n_jobs, sp, lds0, stream)
-                           : launch_sigma0_t<T, false>(single, jobs_dev, n_jobs, sp, lds0, stream);
-    if (e != hipSuccess) g_launch_what = "sigma_0 stage kernel";
-    if (e != hipSuccess || total_tiles == 0) return e;
-    if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
+    const int n_s0 = batched ? n_jobs : 1;  // sigma_0 workgroups, one per job
+    hipError_t e;
+    if (total_tiles == 0) {
+        // sigma_0 only; largest N and W of the batch, non-Hermitian staging needs the most LDS
+        const size_t lds0 = sigma0_lds(N, single.t.W, (int)sizeof(T), false, 160 * 1024).total;
+        e = batched ? launch_sigma0_t<T, true>(single, jobs_dev, n_jobs, sp, lds0, stream)
+                    : launch_sigma0_t<T, false>(single, jobs_dev, n_jobs, sp, lds0, stream);
+        if (e != hipSuccess) g_launch_what = "sigma_0 stage kernel";
+        return e;
+    }
     // MFMA path for 16 <= N (real H); FP64 above N = 48 would need more than
-    // 160 KiB of LDS and stays on the FMA path.
+    // 160 KiB of LDS and stays on the FMA path.  sigma_0 rides along with an
+    // FMA-path launch where its LDS fits; the MFMA kernel keeps its registers
+    // and sigma_0 gets its own launch.
     const int nb = bulk_mfma_blocks(N, single.t.h_complex != 0, sizeof(T) == 8 ? 0 : 1);
     if (nb > 0) {
+        const size_t lds0 = sigma0_lds(N, single.t.W, (int)sizeof(T), false, 160 * 1024).total;
+        e = batched ? launch_sigma0_t<T, true>(single, jobs_dev, n_jobs, sp, lds0, stream)
+                    : launch_sigma0_t<T, false>(single, jobs_dev, n_jobs, sp, lds0, stream);
+        if (e != hipSuccess) {
+            g_launch_what = "sigma_0 stage kernel";
+            return e;
+        }
+        if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
         e = launch_mfma<T>(nb, single.herm != 0, single, jobs_dev, n_jobs, total_tiles, sp, stream);
         if (e != hipSuccess) g_launch_what = "MFMA bulk stage kernel";
     } else {
+        if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
         // batched launches carry the largest tile LDS of the batch
         const size_t lds = single.lds_bytes
                                ? (size_t)single.lds_bytes
                                : fma_lds(N, single.t.W, single.t.D, single.ados_per_tile,
                                          (int)sizeof(T)).total;
         if (single.any_complex_h)
-            e = batched ? launch_fma_t<T, true, true>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream)
-                        : launch_fma_t<T, false, true>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream);
+            e = batched ? launch_fma_t<T, true, true>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream, n_s0)
+                        : launch_fma_t<T, false, true>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream, n_s0);
         else
-            e = batched ? launch_fma_t<T, true, false>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream)
-                        : launch_fma_t<T, false, false>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream);
+            e = batched ? launch_fma_t<T, true, false>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream, n_s0)
+                        : launch_fma_t<T, false, false>(single, jobs_dev, n_jobs, total_tiles, sp, lds, stream, n_s0);
         if (e != hipSuccess) g_launch_what = "FMA bulk stage kernel";
     }
     if (e != hipSuccess) return e;
