@@ -327,7 +327,9 @@ __host__ __device__ inline Sigma0Lds sigma0_lds(int N, int W, int tsize, bool he
 // The sigma_0 stage of job `job` by the whole workgroup (any block size):
 // the body of k_sigma0, and of the extra workgroups of a bulk launch that
 // carries sigma_0 along (lds_cap: the LDS the launch provides).
-template <typename T, bool BATCHED>
+// HC: the job may have a complex H.  The loops stay rolled: the code also
+// runs inside the bulk kernels, whose occupancy its registers would cost.
+template <typename T, bool BATCHED, bool HC>
 __device__ void sigma0_stage(const Job& single, const Job* jobs, int job, const StageSpec& sp,
                              unsigned lds_cap, char* smem_s0) {
     const Job& J = BATCHED ? jobs[job] : single;
@@ -345,7 +347,7 @@ __device__ void sigma0_stage(const Job& single, const Job* jobs, int job, const 
     T* sRows = reinterpret_cast<T*>(smem_s0 + L.rows);  // [W][N] complex
     T* sCols = reinterpret_cast<T*>(smem_s0 + L.cols);  // [W][N] complex
     const int tid = threadIdx.x;
-    const bool hc = t.h_complex != 0;
+    const bool hc = HC && t.h_complex != 0;
     const NbSrc<T> nbs{J.sig0[sp.in], J.rest[sp.in], N};
     for (int e = tid; e < NN; e += blockDim.x) {
         sH[2 * e] = G(t.h_re)[e];
@@ -381,11 +383,13 @@ __device__ void sigma0_stage(const Job& single, const Job* jobs, int job, const 
     if (sp.record_initial && tid == 0 && *G(J.step) == 0) record_sigma0(J, sS, 0);
 
     const double h = sp.hmul * J.dt;
+#pragma unroll 1
     for (int e = tid; e < NN; e += blockDim.x) {
         const int i = e / N, j = e - (e / N) * N;
         // -i [H, sigma_0] (the damping vanishes at u = 0)
         double cr = 0, ci = 0;
         if (hc) {
+#pragma unroll 1
             for (int k = 0; k < N; ++k) {
                 const double hr = sH[2 * (i * N + k)], hi = sH[2 * (i * N + k) + 1];
                 const double xr = sS[2 * (k * N + j)], xi = sS[2 * (k * N + j) + 1];
@@ -395,6 +399,7 @@ __device__ void sigma0_stage(const Job& single, const Job* jobs, int job, const 
                 ci += hr * xi + hi * xr - (yr * gi + yi * gr);
             }
         } else {
+#pragma unroll 1
             for (int k = 0; k < N; ++k) {
                 const double hik = sH[2 * (i * N + k)], hkj = sH[2 * (k * N + j)];
                 cr += hik * sS[2 * (k * N + j)] - sS[2 * (i * N + k)] * hkj;
@@ -461,7 +466,7 @@ __global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int
                                                 StageSpec sp, unsigned lds_cap) {
     extern __shared__ char smem_s0[];
     (void)n_jobs;
-    sigma0_stage<T, BATCHED>(single, jobs, blockIdx.x, sp, lds_cap, smem_s0);
+    sigma0_stage<T, BATCHED, true>(single, jobs, blockIdx.x, sp, lds_cap, smem_s0);
 }
 
 // H (shifted, rad/fs) in the stage precision: FP32 kernels read the FP32 copy.
@@ -497,7 +502,7 @@ __global__ __launch_bounds__(kFmaBlock) __attribute__((amdgpu_waves_per_eu(
     if constexpr (sizeof(T) == 4) {
         if ((int)blockIdx.x < s0_blocks) {
             // the first workgroups carry the sigma_0 stage along
-            sigma0_stage<T, BATCHED>(single, jobs, blockIdx.x, sp, lds_total, smem_raw);
+            sigma0_stage<T, BATCHED, HC>(single, jobs, blockIdx.x, sp, lds_total, smem_raw);
             return;
         }
     }
@@ -771,10 +776,17 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute
                                                                              int n_jobs,
                                                                              StageSpec sp,
                                                                              int total_tiles,
-                                                                             unsigned lds_stride) {
+                                                                             unsigned lds_stride,
+                                                                             int s0_blocks,
+                                                                             unsigned lds_total) {
     constexpr int NT = 128 * NB;  // threads per ADO
     constexpr int AW = mfma_ados_per_wg<T, NB>();
     extern __shared__ char smem_raw[];
+    if ((int)blockIdx.x < s0_blocks) {
+        // the first workgroups carry the sigma_0 stage along (real H on this path)
+        sigma0_stage<T, BATCHED, false>(single, jobs, blockIdx.x, sp, lds_total, smem_raw);
+        return;
+    }
     using L = MfmaLds<T, NB, HERM>;
     constexpr int NP = L::NP, LS = L::LS, LX = L::LX, PLANE = L::PLANE, XPLANE = L::XPLANE;
     constexpr int KS = 4 * NB;      // k-steps of 4
@@ -789,7 +801,7 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute
     const int tid = (int)threadIdx.x - sub * NT;
     const int lane = tid & 63, wave = tid >> 6;
     const int mt = wave >> 1, half = wave & 1;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x) * AW + sub;
+    const int tile = xcd_remap(blockIdx.x - s0_blocks, gridDim.x - s0_blocks) * AW + sub;
     // A half without an ADO still takes part in every barrier.
     const bool active = tile < total_tiles;
     const Job& J = JobOf<BATCHED>::get(single, jobs, n_jobs, active ? tile : total_tiles - 1);
@@ -1199,7 +1211,7 @@ static hipError_t sigma0_ride_along(const Job& single, const Job* jobs_dev, int 
 
 template <typename T, int NB, bool HERM, bool BATCHED, int NBASE>
 static hipError_t launch_mfma_t(const Job& single, const Job* jobs_dev, int n_jobs,
-                                int total_tiles, const StageSpec& sp, hipStream_t stream) {
+                                int total_tiles, const StageSpec& sp, hipStream_t stream, int n_s0) {
     const void* fn = reinterpret_cast<const void*>(&k_bulk_mfma<T, NB, HERM, BATCHED, NBASE>);
     static bool attr_set = false;
     if (!attr_set) {
@@ -1211,50 +1223,56 @@ static hipError_t launch_mfma_t(const Job& single, const Job* jobs_dev, int n_jo
     constexpr int AW = mfma_ados_per_wg<T, NB>();
     const unsigned stride =
         (unsigned)((MfmaLds<T, NB, HERM>::bytes(single.t.N, single.t.W, single.t.D) + 15) & ~(size_t)15);
-    hipLaunchKernelGGL((k_bulk_mfma<T, NB, HERM, BATCHED, NBASE>), dim3((total_tiles + AW - 1) / AW),
-                       dim3(128 * NB * AW), (size_t)stride * AW, stream, single, jobs_dev, n_jobs, sp,
-                       total_tiles, stride);
+    // sigma_0 rides along only within the bulk workgroups' own LDS
+    size_t lds = (size_t)stride * AW;
+    int extra = 0;
+    hipError_t e = sigma0_ride_along<T, BATCHED>(single, jobs_dev, n_jobs, n_s0, true, sp, lds, stream,
+                                                 &extra, &lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_bulk_mfma<T, NB, HERM, BATCHED, NBASE>),
+                       dim3(extra + (total_tiles + AW - 1) / AW), dim3(128 * NB * AW), lds, stream,
+                       single, jobs_dev, n_jobs, sp, total_tiles, stride, extra, (unsigned)lds);
     return hipGetLastError();
 }
 
 template <typename T, int NB, bool HERM, bool BATCHED>
 static hipError_t launch_mfma_b(const Job& single, const Job* jobs_dev, int n_jobs,
-                                int total_tiles, const StageSpec& sp, hipStream_t stream) {
+                                int total_tiles, const StageSpec& sp, hipStream_t stream, int n_s0) {
     if (sp.nbase <= 1)
         return launch_mfma_t<T, NB, HERM, BATCHED, 1>(single, jobs_dev, n_jobs, total_tiles, sp,
-                                                      stream);
+                                                      stream, n_s0);
     return launch_mfma_t<T, NB, HERM, BATCHED, 3>(single, jobs_dev, n_jobs, total_tiles, sp,
-                                                  stream);
+                                                  stream, n_s0);
 }
 
 template <typename T, int NB>
 static hipError_t launch_mfma_nb(bool herm, bool batched, const Job& single, const Job* jobs_dev,
                                  int n_jobs, int total_tiles, const StageSpec& sp,
-                                 hipStream_t stream) {
+                                 hipStream_t stream, int n_s0) {
     if (herm)
         return batched ? launch_mfma_b<T, NB, true, true>(single, jobs_dev, n_jobs, total_tiles,
-                                                          sp, stream)
+                                                          sp, stream, n_s0)
                        : launch_mfma_b<T, NB, true, false>(single, jobs_dev, n_jobs, total_tiles,
-                                                           sp, stream);
+                                                           sp, stream, n_s0);
     return batched ? launch_mfma_b<T, NB, false, true>(single, jobs_dev, n_jobs, total_tiles, sp,
-                                                       stream)
+                                                       stream, n_s0)
                    : launch_mfma_b<T, NB, false, false>(single, jobs_dev, n_jobs, total_tiles, sp,
-                                                        stream);
+                                                        stream, n_s0);
 }
 
 template <typename T>
 static hipError_t launch_mfma(int nb, bool herm, const Job& single, const Job* jobs_dev,
                               int n_jobs, int total_tiles, const StageSpec& sp,
-                              hipStream_t stream) {
+                              hipStream_t stream, int n_s0) {
     const bool batched = jobs_dev != nullptr;
     switch (nb) {
-        case 1: return launch_mfma_nb<T, 1>(herm, batched, single, jobs_dev, n_jobs, total_tiles, sp, stream);
-        case 2: return launch_mfma_nb<T, 2>(herm, batched, single, jobs_dev, n_jobs, total_tiles, sp, stream);
-        case 3: return launch_mfma_nb<T, 3>(herm, batched, single, jobs_dev, n_jobs, total_tiles, sp, stream);
+        case 1: return launch_mfma_nb<T, 1>(herm, batched, single, jobs_dev, n_jobs, total_tiles, sp, stream, n_s0);
+        case 2: return launch_mfma_nb<T, 2>(herm, batched, single, jobs_dev, n_jobs, total_tiles, sp, stream, n_s0);
+        case 3: return launch_mfma_nb<T, 3>(herm, batched, single, jobs_dev, n_jobs, total_tiles, sp, stream, n_s0);
         case 4:
             // FP64 above 48 states takes the FMA kernel (LDS)
             if constexpr (sizeof(T) == 4)
-                return launch_mfma_nb<T, 4>(herm, batched, single, jobs_dev, n_jobs, total_tiles, sp, stream);
+                return launch_mfma_nb<T, 4>(herm, batched, single, jobs_dev, n_jobs, total_tiles, sp, stream, n_s0);
             return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
@@ -1303,20 +1321,12 @@ static hipError_t launch_stage_t(const Job& single, const Job* jobs_dev, int n_j
         return e;
     }
     // MFMA path for 16 <= N (real H); FP64 above N = 48 would need more than
-    // 160 KiB of LDS and stays on the FMA path.  sigma_0 rides along with an
-    // FMA-path launch where its LDS fits; the MFMA kernel keeps its registers
-    // and sigma_0 gets its own launch.
+    // 160 KiB of LDS and stays on the FMA path.  sigma_0 rides along with the
+    // bulk launch where its LDS fits.
     const int nb = bulk_mfma_blocks(N, single.t.h_complex != 0, sizeof(T) == 8 ? 0 : 1);
     if (nb > 0) {
-        const size_t lds0 = sigma0_lds(N, single.t.W, (int)sizeof(T), false, 160 * 1024).total;
-        e = batched ? launch_sigma0_t<T, true>(single, jobs_dev, n_jobs, sp, lds0, stream)
-                    : launch_sigma0_t<T, false>(single, jobs_dev, n_jobs, sp, lds0, stream);
-        if (e != hipSuccess) {
-            g_launch_what = "sigma_0 stage kernel";
-            return e;
-        }
         if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
-        e = launch_mfma<T>(nb, single.herm != 0, single, jobs_dev, n_jobs, total_tiles, sp, stream);
+        e = launch_mfma<T>(nb, single.herm != 0, single, jobs_dev, n_jobs, total_tiles, sp, stream, n_s0);
         if (e != hipSuccess) g_launch_what = "MFMA bulk stage kernel";
     } else {
         if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
