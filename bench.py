@@ -90,7 +90,7 @@ def parse():
     ap.add_argument("--copy-gib", type=float, default=4.0,
                     help="--workload copy: bytes read (and written) per copy")
     ap.add_argument("--precision", default="fp32_mixed", choices=["fp32_mixed", "fp64"])
-    ap.add_argument("--cpu-baseline-seconds", type=float, default=10.0,
+    ap.add_argument("--cpu-baseline-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample (0 disables it)")
     ap.add_argument("--serve-requests", type=int, default=128)
     ap.add_argument("--serve-steps", type=int, default=1000)
@@ -113,14 +113,20 @@ def cpu_baseline(prob, target_s):
     t0 = time.perf_counter()
     oracle.rhs(prob, x, 0, 0)  # model and table construction only
     t_setup = time.perf_counter() - t0
+    # probe with growing blocks, then one timed block sized to target_s
     k = 1
     while True:
         t0 = time.perf_counter()
         oracle.rhs(prob, x, n - k, n)
         dt = time.perf_counter() - t0 - t_setup
-        if dt * 2 > target_s or k >= n:
+        if dt > 0.1 * target_s or k >= n:
             break
-        k = min(n, max(k * 2, int(k * target_s / max(dt, 1e-3) * 0.6)))
+        k = min(n, max(k * 2, int(k * 0.2 * target_s / max(dt, 1e-3))))
+    if k < n:
+        k = min(n, max(k, int(k * target_s / max(dt, 1e-6))))
+        t0 = time.perf_counter()
+        oracle.rhs(prob, x, n - k, n)
+        dt = time.perf_counter() - t0 - t_setup
     per_rhs = max(dt, 1e-9) / k
     return {"value": 1.0 / (4.0 * per_rhs), "unit": "ADO-updates/s", "cores": 1,
             "kind": "oracle",
