@@ -12,7 +12,9 @@ namespace heom {
 
 constexpr int kMaxStates = 64;
 constexpr int kBlock = 256;
-constexpr int kFmaBlock = 256;  // threads of an FMA-path stage workgroup
+// Threads of an FMA-path stage workgroup: FP32 256, FP64 64 (its registers
+// allow fewer waves per SIMD, and smaller workgroups fill them better).
+__host__ __device__ constexpr int fma_block(int tsize) { return tsize == 4 ? 256 : 64; }
 
 // Device pointers into the caller's tables buffer, plus the scalars the
 // kernels need.  Everything here is written once by heom_build_hierarchy.
@@ -108,7 +110,7 @@ __host__ __device__ inline FmaLds fma_lds(int N, int W, int D, int GA, int tsize
     return L;
 }
 
-// ADOs per FMA-path tile: kFmaBlock / N^2 threads' worth, reduced to fit 64 KiB of LDS.
+// ADOs per FMA-path tile: fma_block / N^2 threads' worth, reduced to fit 64 KiB of LDS.
 int bulk_ados_per_tile(int N, int W, int D, int tsize);
 // Name of the kernel whose launch failed in the last launch_stage call on this thread.
 const char* last_launch_failure();
