@@ -89,7 +89,7 @@ def parse():
                     choices=sorted(WORKLOADS) + ["serve", "copy"])
     ap.add_argument("--copy-gib", type=float, default=4.0,
                     help="--workload copy: bytes read (and written) per copy")
-    ap.add_argument("--precision", default="fp32_mixed", choices=["fp32_mixed", "fp64"])
+    ap.add_argument("--precision", default="fp32_mixed", choices=["fp32_mixed", "fp32_herm", "fp64"])
     ap.add_argument("--cpu-baseline-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample (0 disables it)")
     ap.add_argument("--serve-requests", type=int, default=128)
@@ -290,7 +290,8 @@ def main():
     from paper_1803_03498_amd import _abi
 
     prob = WORKLOADS[args.workload]()
-    precision = heom.FP32_MIXED if args.precision == "fp32_mixed" else heom.FP64
+    precision = {"fp32_mixed": heom.FP32_MIXED, "fp32_herm": heom.FP32_HERM,
+                 "fp64": heom.FP64}[args.precision]
     steps = args.steps if args.steps is not None else (50 if args.workload == "aggregate48" else 200)
     warmup = args.warmup if args.warmup is not None else 5
     torch.cuda.set_device(0)
@@ -354,14 +355,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if precision == heom.FP32_MIXED else "f64",
+        "dtype": "f64" if precision == heom.FP64 else "f32",
         "data": "synthetic",
         "hbm_GBps_algorithmic": hbm_gbs,
         "config": {
             "workload": "%s: %d sites, W=%d modes, depth %d, %d ADOs of %dx%d %s; RK4 dt=%g fs"
                         % (args.workload, N, h.W, prob["depth"], n, N, N,
-                           "complex64 (sigma_0 complex128)" if precision == heom.FP32_MIXED
-                           else "complex128", prob["dt_fs"]),
+                           {heom.FP32_MIXED: "complex64 (sigma_0 complex128)",
+                            heom.FP32_HERM: "Hermitian-packed real float32 (sigma_0 complex128)",
+                            heom.FP64: "complex128"}[precision], prob["dt_fs"]),
             "n_ado": n, "n_states": N, "n_modes": h.W, "depth": prob["depth"],
             "precision": args.precision, "record_every": rec_every,
             "bytes_per_step_algorithmic": step_bytes,

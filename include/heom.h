@@ -57,8 +57,14 @@ enum {
 /* Precision of the hierarchy state. */
 enum {
     HEOM_FP64 = 0,        /* every ADO complex128                                   */
-    HEOM_FP32_MIXED = 1   /* sigma_0 complex128 with FP64 RK4 and FP64 observables; */
+    HEOM_FP32_MIXED = 1,  /* sigma_0 complex128 with FP64 RK4 and FP64 observables; */
                           /* ADOs u >= 1 complex64 with FP32 arithmetic             */
+    HEOM_FP32_HERM = 2    /* as HEOM_FP32_MIXED for Hermitian ADOs (population runs,
+                             hermitian = 1 only), each ADO u >= 1 stored packed as one
+                             real FP32 N x N matrix P: P[i][j] = Re sigma[i][j] for
+                             i <= j and P[i][j] = Im sigma[j][i] for i > j, half the
+                             bytes of complex64.  Needs the matrix-core path (real H,
+                             16 <= N <= 64); not accepted by heom_submit.           */
 };
 
 /* Test switches (heom_problem.flags).  Both the library and the oracle honour them. */
@@ -96,7 +102,7 @@ typedef struct {
     const heom_bath* baths; /* [B]                                              */
     double temperature_K;   /* T > 0                                            */
     int32_t depth;          /* truncation depth D >= 0 (sum of tuple <= D)      */
-    int32_t precision;      /* HEOM_FP64 or HEOM_FP32_MIXED                     */
+    int32_t precision;      /* HEOM_FP64, HEOM_FP32_MIXED or HEOM_FP32_HERM     */
     uint32_t flags;         /* HEOM_FLAG_*                                      */
 } heom_problem;
 
@@ -107,7 +113,7 @@ typedef struct {
     int32_t n_states;       /* N                                          */
     int32_t n_modes;        /* W = sum over baths of (1 + M_b)            */
     int32_t depth;          /* D                                          */
-    int32_t elem_bytes;     /* bytes per complex element of ADOs u >= 1   */
+    int32_t elem_bytes;     /* bytes per element of ADOs u >= 1 (16/8/4)  */
     size_t tables_bytes;    /* device bytes for heom_build_hierarchy      */
     size_t sigma0_bytes;    /* N*N*16                                     */
     size_t rest_bytes;      /* (n_ado - 1) * N*N * elem_bytes             */
@@ -119,7 +125,7 @@ typedef struct {
 } heom_info;
 
 /* A hierarchy state: sigma_0 (complex128 [N][N]) and ADOs 1..n_ado-1
- * (complex128 or complex64 [n_ado-1][N][N] by precision).  Both device
+ * (complex128, complex64 or packed real FP32 [n_ado-1][N][N] by precision).  Both device
  * pointers, 256-byte aligned, caller-owned.  In HEOM_FP64, rest may equal
  * sigma0 + N*N complex elements (one contiguous array). */
 typedef struct {

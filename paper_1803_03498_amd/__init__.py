@@ -15,9 +15,9 @@ import ctypes
 import numpy as np
 
 from . import _abi
-from ._abi import FP32_MIXED, FP64, OBS_DIPOLE, OBS_POPULATION, HeomError, check, load
+from ._abi import FP32_HERM, FP32_MIXED, FP64, OBS_DIPOLE, OBS_POPULATION, HeomError, check, load
 
-__all__ = ["FP64", "FP32_MIXED", "OBS_POPULATION", "OBS_DIPOLE", "HeomError", "Problem", "plan",
+__all__ = ["FP64", "FP32_MIXED", "FP32_HERM", "pack_hermitian", "unpack_hermitian", "OBS_POPULATION", "OBS_DIPOLE", "HeomError", "Problem", "plan",
            "Hierarchy", "Server", "spectrum", "load"]
 
 
@@ -80,6 +80,24 @@ def _info_struct(d):
     return info
 
 
+def pack_hermitian(x):
+    """Hermitian matrices [..., N, N] -> the packed real layout of the
+    FP32_HERM storage: P[i][j] = Re x[i][j] (i <= j), Im x[j][i] (i > j)."""
+    x = np.asarray(x)
+    upper = np.triu(np.ones(x.shape[-2:], bool))
+    return np.where(upper, x.real, np.swapaxes(x.imag, -1, -2))
+
+
+def unpack_hermitian(p):
+    """Inverse of pack_hermitian: complex128 [..., N, N]."""
+    p = np.asarray(p, np.float64)
+    pt = np.swapaxes(p, -1, -2)
+    i, j = np.indices(p.shape[-2:])
+    re = np.where(i <= j, p, pt)
+    im = np.where(i < j, pt, np.where(i > j, -p, 0.0))
+    return re + 1j * im
+
+
 class Hierarchy:
     """A hierarchy built on the current GPU (heom_build_hierarchy)."""
 
@@ -112,7 +130,12 @@ class Hierarchy:
     @property
     def rest_dtype(self):
         torch = _torch()
-        return torch.complex128 if self.precision == FP64 else torch.complex64
+        return {FP64: torch.complex128, FP32_MIXED: torch.complex64}.get(self.precision,
+                                                                         torch.float32)
+
+    @property
+    def _host_rest_dtype(self):
+        return {FP64: np.complex128, FP32_MIXED: np.complex64}.get(self.precision, np.float32)
 
     def new_state(self, rho0=None):
         """(sigma0 complex128 [N,N], rest [n_ado-1,N,N]) on the GPU, zeroed;
@@ -130,16 +153,17 @@ class Hierarchy:
         torch = _torch()
         full = np.asarray(full)
         s0 = torch.as_tensor(np.ascontiguousarray(full[0], dtype=np.complex128)).cuda()
-        rest = torch.as_tensor(np.ascontiguousarray(
-            full[1:], dtype=np.complex128 if self.precision == FP64 else np.complex64)).cuda()
+        rest = full[1:] if self.precision != FP32_HERM else pack_hermitian(full[1:])
+        rest = torch.as_tensor(np.ascontiguousarray(rest, dtype=self._host_rest_dtype)).cuda()
         return s0, rest
 
-    @staticmethod
-    def state_to_numpy(state):
+    def state_to_numpy(self, state):
+        """Host complex128 [n_ado, N, N] of a device state."""
         s0, rest = state
         out = np.zeros((1 + rest.shape[0],) + tuple(s0.shape), np.complex128)
         out[0] = s0.cpu().numpy()
-        out[1:] = rest.cpu().numpy()
+        r = rest.cpu().numpy()
+        out[1:] = unpack_hermitian(r) if self.precision == FP32_HERM else r
         return out
 
     @staticmethod
@@ -202,15 +226,14 @@ class Hierarchy:
     def get_state(self, state):
         s0, rest = state
         h0 = np.zeros((self.N, self.N), np.complex128)
-        hr = np.zeros(tuple(rest.shape), np.complex128 if self.precision == FP64 else np.complex64)
+        hr = np.zeros(tuple(rest.shape), self._host_rest_dtype)
         check(load().heom_get_state(self.handle, self._st(state), h0.ctypes.data,
                                     hr.ctypes.data if hr.size else None, _stream_handle()))
         return h0, hr
 
     def set_state(self, state, host_sigma0, host_rest):
         h0 = np.ascontiguousarray(host_sigma0, dtype=np.complex128)
-        hr = np.ascontiguousarray(host_rest, dtype=np.complex128 if self.precision == FP64
-                                  else np.complex64)
+        hr = np.ascontiguousarray(host_rest, dtype=self._host_rest_dtype)
         check(load().heom_set_state(self.handle, self._st(state), h0.ctypes.data,
                                     hr.ctypes.data if hr.size else None, _stream_handle()))
 

@@ -15,6 +15,7 @@ STATUS_NAMES = {0: "HEOM_OK", 1: "HEOM_PENDING", -1: "HEOM_E_INVAL", -2: "HEOM_E
                 -6: "HEOM_E_UNSTABLE", -7: "HEOM_E_NOTFOUND", -8: "HEOM_E_CANCELLED"}
 FP64 = 0
 FP32_MIXED = 1
+FP32_HERM = 2  # Hermitian-packed real FP32 ADOs (Hermitian runs, matrix-core path)
 OBS_POPULATION = 0
 OBS_DIPOLE = 1
 

@@ -48,12 +48,17 @@ constexpr double kBoltzmannCm = 0.6950348004;
 constexpr double kRk4RealLimit = 2.78;  // RK4 stability interval on the negative real axis
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+// one complex64 copy of n ADOs of N x N
+constexpr size_t mirror_bytes(int64_t n, int N) {
+    return align256(std::max<size_t>((size_t)n * N * N * 8, 1));
+}
 
 // Everything derived from a problem on the host.
 struct Derived {
     int N = 0, W = 0, D = 0, B = 0, precision = 0;
     uint32_t flags = 0;
     int64_t n_ado = 0, n_plus = 0;
+    int64_t n_low = 0;  // ADOs at levels 1..D-1
     bool h_complex = false;
     std::vector<double> h_re, h_im;  // shifted, rad/fs
     std::vector<int32_t> mode_site;
@@ -139,7 +144,8 @@ heom_status derive(const heom_problem* p, Derived& d) {
     if (!p->h_re_cm) return fail(HEOM_E_INVAL, "h_re_cm is NULL");
     if (p->depth < 0) return fail(HEOM_E_INVAL, "depth < 0");
     if (p->depth > 255) return fail(HEOM_E_RANGE, "depth > 255");
-    if (p->precision != HEOM_FP64 && p->precision != HEOM_FP32_MIXED)
+    if (p->precision != HEOM_FP64 && p->precision != HEOM_FP32_MIXED &&
+        p->precision != HEOM_FP32_HERM)
         return fail(HEOM_E_INVAL, "precision %d unknown", p->precision);
     if (p->flags & ~15u) return fail(HEOM_E_INVAL, "unknown flags 0x%x", p->flags);
     if (!is_finite(p->temperature_K) || !(p->temperature_K > 0.0))
@@ -220,6 +226,9 @@ heom_status derive(const heom_problem* p, Derived& d) {
         d.h_im[e] = hi[e] * kCmToRadFs;
         if (hi[e] != 0.0) d.h_complex = true;
     }
+    if (d.precision == HEOM_FP32_HERM && heom::bulk_mfma_blocks(N, d.h_complex, d.precision) == 0)
+        return fail(HEOM_E_INVAL,
+                    "Hermitian-packed storage needs the matrix-core path (real H, 16 <= N <= 64)");
     // rescaled coupling weights (ADO rescaling substitution); |c| = 0 uses scale 1
     const int D = d.D;
     d.plus_coef.assign((size_t)W * (D + 1), 0.0);
@@ -245,6 +254,7 @@ heom_status derive(const heom_problem* p, Derived& d) {
     if (n_ado >= (int64_t(1) << 31)) return fail(HEOM_E_RANGE, "n_ado >= 2^31");
     d.n_ado = n_ado;
     d.n_plus = (D == 0) ? 0 : (int64_t)W * d.binom[(size_t)(D - 1) * (W + 1) + W];
+    d.n_low = (D == 0) ? 0 : d.binom[(size_t)(D - 1) * (W + 1) + W] - 1;
     // Gershgorin-type bound on the generator, for the RK4 step-size check:
     // commutator 2||H||_inf, damping D max gamma, correction 2 max Delta, and
     // per element the couplings of the modes of two states.
@@ -282,7 +292,7 @@ void fill_info(const Derived& d, heom_info* info) {
     info->n_states = d.N;
     info->n_modes = d.W;
     info->depth = d.D;
-    info->elem_bytes = d.precision == HEOM_FP64 ? 16 : 8;
+    info->elem_bytes = d.precision == HEOM_FP64 ? 16 : d.precision == HEOM_FP32_MIXED ? 8 : 4;
     info->tables_bytes = L.total;
     const size_t NN = (size_t)d.N * d.N;
     info->sigma0_bytes = NN * 16;
@@ -291,6 +301,8 @@ void fill_info(const Derived& d, heom_info* info) {
     info->bulk_kernel = heom::bulk_mfma_blocks(d.N, d.h_complex, d.precision) > 0 ? 1 : 0;
     info->work_bytes = 1024 + align256(d.N * 8) +
                        3 * (align256(info->sigma0_bytes) + align256(std::max<size_t>(info->rest_bytes, 1)));
+    // Hermitian-packed storage: two complex64 copies of the levels 1..D-1
+    if (d.precision == HEOM_FP32_HERM) info->work_bytes += 2 * mirror_bytes(d.n_low, d.N);
 }
 
 int gfx950_device_check() {
@@ -495,6 +507,7 @@ heom::Job base_job(const heom_hierarchy* h) {
     j.any_complex_h = h->t.h_complex;
     j.dt = 1.0;
     j.tile_begin = 0;
+    j.n_low = (int32_t)h->d.n_low;
     j.ados_per_tile =
         heom::bulk_mfma_blocks(h->t.N, h->t.h_complex != 0, h->d.precision)
             ? 1
@@ -537,6 +550,12 @@ Job bind_workspace(const heom_hierarchy* h, heom_state io, char* w, double dt, i
     }
     j.sig0[0] = io.sigma0;
     j.rest[0] = io.rest;
+    if (h->d.precision == HEOM_FP32_HERM) {
+        for (int m = 0; m < 2; ++m) {
+            j.mirror[m] = w + off;
+            off += mirror_bytes(h->d.n_low, N);
+        }
+    }
     j.records = reinterpret_cast<double*>(w + off);
     j.n_rec_max = heom_record_count(n_steps, record_every);
     j.rec_every = record_every;
@@ -602,6 +621,8 @@ heom_status heom_rhs(const heom_hierarchy* h, heom_state in, heom_state out, int
     heom_status s;
     if ((s = check_state(h, in, "in")) != HEOM_OK) return s;
     if ((s = check_state(h, out, "out")) != HEOM_OK) return s;
+    if (h->d.precision == HEOM_FP32_HERM && !hermitian)
+        return fail(HEOM_E_INVAL, "Hermitian-packed storage holds Hermitian ADOs only");
     heom::Job j = base_job(h);
     j.herm = hermitian ? 1 : 0;
     j.sig0[0] = in.sigma0;
@@ -635,6 +656,8 @@ heom_status heom_propagate(const heom_hierarchy* h, heom_state io, void* work_de
         return fail(HEOM_E_INVAL, "observable kind %d unknown", kind);
     if (kind == HEOM_OBS_DIPOLE && (!obs->mu || obs->ground < 0 || obs->ground >= h->t.N))
         return fail(HEOM_E_INVAL, "dipole observable needs mu and a ground index in range");
+    if (h->d.precision == HEOM_FP32_HERM && !hermitian)
+        return fail(HEOM_E_INVAL, "Hermitian-packed storage holds Hermitian ADOs only");
     if (dt_fs * h->d.rate_bound > kRk4RealLimit)
         return fail(HEOM_E_UNSTABLE, "dt=%g fs times the rate bound %g /fs exceeds %g", dt_fs,
                     h->d.rate_bound, kRk4RealLimit);
@@ -660,6 +683,16 @@ heom_status heom_propagate(const heom_hierarchy* h, heom_state io, void* work_de
     heom::rk4_stage_specs(sp);
 
     const int tiles = h->t.n_ado > 1 ? j.n_tiles : 0;
+    if (h->d.precision == HEOM_FP32_HERM && j.n_low > 0 && tiles > 0) {
+        // complex copies of the lower levels, alternating between the two
+        // buffers: stage k reads the copy the previous stage wrote
+        hipError_t e = heom::launch_pk_mirror(io.rest, j.mirror[0], N, j.n_low, st);
+        if (e != hipSuccess) return fail(HEOM_E_DEVICE, "mirror launch: %s", hipGetErrorString(e));
+        for (int k = 0; k < 4; ++k) {
+            sp[k].mirror_in = 1 + (k & 1);
+            sp[k].mirror_out = 2 - (k & 1);
+        }
+    }
     const bool timed = g_timing.enabled.load() && tiles > 0;
     std::vector<hipEvent_t> ev;
     if (timed) {

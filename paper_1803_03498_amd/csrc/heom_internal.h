@@ -60,6 +60,11 @@ struct Job {
     int32_t ados_per_tile;
     uint32_t lds_bytes;           // batched launches: LDS of the largest tile (0 = derive)
     int32_t any_complex_h;        // some job of the launch has a complex H
+    // Hermitian-packed storage only: complex64 copies [n_low][N][N] of the
+    // ADOs 1..n_low (levels 1..D-1, the only "-" neighbours besides sigma_0),
+    // so that "-" rows are read contiguously; see StageSpec::mirror_in.
+    void* mirror[2];
+    int32_t n_low;
     double* records;              // [n_rec_max][rec_doubles]
     const double* mu;             // [N] (dipole observable)
     int64_t* step;                // device step counter
@@ -79,11 +84,17 @@ struct StageSpec {
     double hmul;
     int32_t record_initial;  // record sigma_0 of `in` when the step counter is 0
     int32_t record_after;    // advance the step counter, record the output
+    // Hermitian-packed storage: 1 + index into Job::mirror of the copy of
+    // `in` to read "-" rows from and of the copy of `out` to write (0 = none;
+    // then "-" rows and columns are read from the packed ADOs).
+    int32_t mirror_in, mirror_out;
 };
 
 // Kernel launchers (heom_kernels.hip).  All enqueue on `stream` and return the
 // HIP error of the launch.
 hipError_t launch_enumerate(const Tables& t, hipStream_t stream);
+// Complex64 copy of the packed ADOs 1..n into `mirror` (Hermitian-packed storage).
+hipError_t launch_pk_mirror(const void* packed_rest, void* mirror, int N, int n, hipStream_t stream);
 // ev_begin/ev_end (may be null) bracket the bulk-kernel launch.
 hipError_t launch_stage(const Job& single, const Job* jobs_dev, int n_jobs, int total_tiles,
                         int precision, const StageSpec& sp, hipStream_t stream,

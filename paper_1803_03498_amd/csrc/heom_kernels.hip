@@ -213,6 +213,33 @@ __device__ __forceinline__ cpx<T> load_nb(const NbSrc<T>& s, int nb, int r, int 
     return ld<T>(s.rest, (size_t)(nb - 1) * s.N * s.N + (size_t)r * s.N + c);
 }
 
+// Hermitian-packed storage (FP32): ADO u >= 1 is the real N x N array
+//   P[i][j] = Re sigma(i, j) for i <= j,   P[i][j] = Im sigma(j, i) for i > j,
+// half the bytes of the complex form.  With a = min(r, c), b = max(r, c):
+//   sigma(r, c) = (P[a][b], +P[b][a]) above the diagonal, (P[a][b], -P[b][a])
+//   below it, (P[a][a], 0) on it.
+// Packed value P_nb[r][c] of neighbour nb (index 0: the complex128 sigma_0,
+// whose upper triangle is taken).
+__device__ __forceinline__ float pk_nb(const NbSrc<float>& s, int nb, int r, int c) {
+    if (nb == 0) {
+        const cpx<double> v = ld<double>(s.sig0, (size_t)min(r, c) * s.N + max(r, c));
+        return (float)(r <= c ? v.re : v.im);
+    }
+    return G(reinterpret_cast<const float*>(s.rest))[(size_t)(nb - 1) * s.N * s.N + (size_t)r * s.N + c];
+}
+
+// Element (r, c) of neighbour nb, from complex (PK false) or packed storage.
+template <typename T, bool PK>
+__device__ __forceinline__ cpx<T> nb_get(const NbSrc<T>& s, int nb, int r, int c) {
+    if constexpr (PK) {
+        if (nb == 0) return load_nb<T>(s, 0, r, c);
+        const T x = pk_nb(s, nb, min(r, c), max(r, c)), y = pk_nb(s, nb, max(r, c), min(r, c));
+        return {x, r < c ? y : (r > c ? -y : (T)0)};
+    } else {
+        return load_nb<T>(s, nb, r, c);
+    }
+}
+
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
     // Workgroups are handed to the 8 XCDs round-robin; give each XCD a
     // contiguous range of tiles so neighbouring ADOs share one L2.
@@ -329,7 +356,7 @@ __host__ __device__ inline Sigma0Lds sigma0_lds(int N, int W, int tsize, bool he
 // carries sigma_0 along (lds_cap: the LDS the launch provides).
 // HC: the job may have a complex H.  The loops stay rolled: the code also
 // runs inside the bulk kernels, whose occupancy its registers would cost.
-template <typename T, bool BATCHED, bool HC>
+template <typename T, bool BATCHED, bool HC, bool PK = false>
 __device__ void sigma0_stage(const Job& single, const Job* jobs, int job, const StageSpec& sp,
                              unsigned lds_cap, char* smem_s0) {
     const Job& J = BATCHED ? jobs[job] : single;
@@ -369,7 +396,7 @@ __device__ void sigma0_stage(const Job& single, const Job* jobs, int job, const 
         for (int idx = tid; idx < W * N; idx += blockDim.x) {
             const int l = idx / N, c = idx - (idx / N) * N;
             const int site = G(t.mode_site)[l];
-            const cpx<T> r = load_nb<T>(nbs, 1 + l, site, c);
+            const cpx<T> r = nb_get<T, PK>(nbs, 1 + l, site, c);
             sRows[2 * idx] = r.re;
             sRows[2 * idx + 1] = r.im;
             if (!herm) {
@@ -424,8 +451,8 @@ __device__ void sigma0_stage(const Job& single, const Job* jobs, int job, const 
                             x = {sCols[2 * (l * N + i)], sCols[2 * (l * N + i) + 1]};
                         }
                     } else {
-                        x = (herm && pass == 1) ? cconj(load_nb<T>(nbs, 1 + l, s, i))
-                                                : load_nb<T>(nbs, 1 + l, i, j);
+                        x = (herm && pass == 1) ? cconj(nb_get<T, PK>(nbs, 1 + l, s, i))
+                                                : nb_get<T, PK>(nbs, 1 + l, i, j);
                     }
                     const double pa = pass == 0 ? sPa[l] : -sPa[l];
                     fr -= pa * (double)x.im;
@@ -461,12 +488,12 @@ __device__ void sigma0_stage(const Job& single, const Job* jobs, int job, const 
     }
 }
 
-template <typename T, bool BATCHED>
+template <typename T, bool BATCHED, bool PK = false>
 __global__ __launch_bounds__(256) void k_sigma0(Job single, const Job* jobs, int n_jobs,
                                                 StageSpec sp, unsigned lds_cap) {
     extern __shared__ char smem_s0[];
     (void)n_jobs;
-    sigma0_stage<T, BATCHED, true>(single, jobs, blockIdx.x, sp, lds_cap, smem_s0);
+    sigma0_stage<T, BATCHED, true, PK>(single, jobs, blockIdx.x, sp, lds_cap, smem_s0);
 }
 
 // H (shifted, rad/fs) in the stage precision: FP32 kernels read the FP32 copy.
@@ -1141,6 +1168,353 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute
     }
 }
 
+
+// Bulk RK4 stage on Hermitian-packed FP32 storage (P as defined at pk_nb).
+// Same thread layout and matrix-core product as k_bulk_mfma on its
+// Hermitian path; the sigma planes are unpacked from P in LDS.  In P-space
+// the right-hand side of element (i, j) is, with X = H sigma = Xr + i Xi:
+//   commutator    i <= j: Xi[i][j] + Xi[j][i];   i > j: Xr[i][j] - Xr[j][i]
+//   damping       -(gamma_u + (Delta_i + Delta_j if i != j)) P[i][j]
+//   "+" modes l   (sum over modes of j - sum over modes of i) w_l P_{u+e_l}[j][i]
+//   "-" link a of state s in {i, j}, i != j:
+//                 lambda nu_a w_a P_{u-e_a}[i][j] + (s == j ? 1 : -1) c_a w_a P_{u-e_a}[j][i]
+//   "-" link a of state s = i = j: 2 lambda nu_a w_a P_{u-e_a}[i][i]
+// (the real and imaginary parts of Z[i][j] + conj(Z[j][i]) in the notation
+// of k_bulk_mfma).  Each thread reads the "+" neighbours at its own (i, j)
+// and hands the weighted sum to element (j, i) through LDS; row s and
+// column s of the first "-" neighbours are staged in LDS while the matrix
+// cores run.  Every global access of an ADO's own data is coalesced.
+template <int NB, int NBASE>
+__global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<float, NB>())) __attribute__((
+    amdgpu_waves_per_eu(mfma_waves_per_eu<float, NB, true>()))) void k_bulk_mfma_pk(Job single,
+                                                                                   StageSpec sp,
+                                                                                   int total_tiles,
+                                                                                   unsigned lds_stride,
+                                                                                   int s0_blocks,
+                                                                                   unsigned lds_total) {
+    using T = float;
+    constexpr int NT = 128 * NB;
+    constexpr int AW = mfma_ados_per_wg<T, NB>();
+    extern __shared__ char smem_raw[];
+    if ((int)blockIdx.x < s0_blocks) {
+        sigma0_stage<T, false, false, true>(single, nullptr, blockIdx.x, sp, lds_total, smem_raw);
+        return;
+    }
+    using L = MfmaLds<T, NB, true>;
+    constexpr int NP = L::NP, LS = L::LS, LX = L::LX, PLANE = L::PLANE, XPLANE = L::XPLANE;
+    constexpr int KS = 4 * NB;
+    constexpr int EPT = 2 * NB;
+    constexpr int RS = NT / NP;
+    constexpr int KP = 2;  // "+" modes per state loaded ahead (more are read late)
+    using acc_t = typename mfma_acc<T>::type;
+
+    const int sub = AW > 1 ? uniform((int)threadIdx.x / NT) : 0;
+    const int tid = (int)threadIdx.x - sub * NT;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int mt = wave >> 1, half = wave & 1;
+    const int tile = xcd_remap(blockIdx.x - s0_blocks, gridDim.x - s0_blocks) * AW + sub;
+    const bool active = tile < total_tiles;
+    const Job& J = single;
+    const Tables& t = J.t;
+    const int N = t.N, NN = N * N, W = t.W, D = t.D, Dm = D > 0 ? D : 1;
+    const int u = active ? 1 + tile : 1;
+    const T* rest_in = reinterpret_cast<const T*>(J.rest[sp.in]);
+    const T* own = rest_in + (size_t)(u - 1) * NN;
+    const NbSrc<T> nbs{J.sig0[sp.in], J.rest[sp.in], N};
+    const int n_rows = L::n_rows(D);
+
+    T* sSre = reinterpret_cast<T*>(smem_raw + (size_t)sub * lds_stride);  // sigma, then Q (stride LX)
+    T* sSim = sSre + PLANE;
+    T* sXre = sSim + PLANE;
+    T* sXim = sXre + XPLANE;
+    T* sRow = sXim + XPLANE;  // [n_rows][N] rows s, then [n_rows][N] columns s
+    T* sCol = sRow + n_rows * N;
+    const T** sPptr = reinterpret_cast<const T**>(sRow + 2 * n_rows * N);  // [W]
+    T* sMml = reinterpret_cast<T*>(sPptr + W);
+    T* sMmc = sMml + Dm;
+    T* sDelta = sMmc + Dm;
+    T* sPa = sDelta + N;
+    int* sBegin = reinterpret_cast<int*>(sPa + W);
+    int* sModes = sBegin + N + 1;
+    int* sMsite = sModes + W;
+    int* sMnb = sMsite + Dm;
+
+    const int r0 = tid / NP, j = tid - (tid / NP) * NP;
+    const bool jin = active && j < N;
+
+    // 1. Own P values (clamped unpredicated loads, zeroed outside N x N), H,
+    //    link tables.
+    T cur[EPT];
+    const int jc = min(j, N - 1);
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int i = r0 + RS * k;
+        const T m = (jin && i < N) ? (T)1 : (T)0;
+        cur[k] = G(own)[min(i, N - 1) * N + jc] * m;
+    }
+    T hreg[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int r = min(16 * mt + (lane & 15), N - 1), c = min(4 * ks + (lane >> 4), N - 1);
+        hreg[ks] = h_entry<T>(t, r * N + c);
+    }
+    const int lev = G(t.level)[u];
+    const T gam = (T)G(t.damping)[u];
+    const bool has_plus = lev < D;
+    int lsite[kPrefRows];
+    T lml[kPrefRows], lmc[kPrefRows];
+#pragma unroll
+    for (int a = 0; a < kPrefRows; ++a) {
+        const size_t at = (size_t)u * Dm + min(a, Dm - 1);
+        lsite[a] = a < Dm ? G(t.mlist_site)[at] : -1;
+        const pair_f w = G(reinterpret_cast<const pair_f*>(t.mlist_w32))[at];
+        lml[a] = w.x;
+        lmc[a] = w.y;
+    }
+    const T* bptr[NBASE];
+#pragma unroll
+    for (int m = 0; m < NBASE; ++m)
+        bptr[m] = reinterpret_cast<const T*>(J.rest[sp.base[m < sp.nbase ? m : 0]]) + (size_t)(u - 1) * NN;
+    for (int a = tid; a < Dm; a += NT) {
+        const pair_d w = G(reinterpret_cast<const pair_d*>(t.mlist_w))[(size_t)u * Dm + a];
+        sMnb[a] = G(reinterpret_cast<const pair_i*>(t.mlist))[(size_t)u * Dm + a].x;
+        sMsite[a] = G(t.mlist_site)[(size_t)u * Dm + a];
+        sMml[a] = (T)w.x;
+        sMmc[a] = (T)w.y;
+    }
+    if (has_plus) {
+        for (int l = tid; l < W; l += NT) {
+            const int nb = G(t.plus)[(size_t)u * W + l];
+            sPptr[l] = rest_in + (size_t)(nb - 1) * NN;
+            sPa[l] = (T)G(t.plus_w)[(size_t)u * W + l];
+            sModes[l] = G(t.state_modes)[l];
+        }
+        for (int x = tid; x <= N; x += NT) sBegin[x] = G(t.state_mode_begin)[x];
+    }
+    for (int x = tid; x < N; x += NT) sDelta[x] = (T)G(t.delta_state)[x];
+    // Unpack into the sigma planes in two passes: P row-major into the X
+    // plane (free until the matrix cores write it), then each thread reads
+    // P[j][i] (odd stride: distinct banks) and writes Re and Im of its own
+    // cells row-major.  Zero outside the N x N block.
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) sXre[(r0 + RS * k) * LX + j] = cur[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int i = r0 + RS * k;
+        const T pt = sXre[j * LX + i];
+        sSre[i * LS + j] = i <= j ? cur[k] : pt;
+        sSim[i * LS + j] = i < j ? pt : (i > j ? -cur[k] : (T)0);
+    }
+    __syncthreads();
+
+    // 2. Row s and column s of the first "-" neighbours in flight; X = H sigma.
+    //    With a complex copy of the input's lower levels, one contiguous row
+    //    s of sigma_{u-e_a} gives both (P[s][c] and P[c][s]); otherwise the
+    //    column is read from the packed ADO.
+    const void* mir_in = sp.mirror_in ? J.mirror[sp.mirror_in - 1] : nullptr;
+    T pre = 0, pre2 = 0;
+    const int nrn = n_rows * N;
+    bool has_pre;
+    if (mir_in) {
+        has_pre = tid < nrn && sMnb[tid / N] >= 0;
+        if (has_pre) {
+            const int a = tid / N, c = tid - (tid / N) * N, s = sMsite[a], nb = sMnb[a];
+            const cpx<T> x = nb == 0 ? load_nb<T>(nbs, 0, s, c) : ld<T>(mir_in, (size_t)(nb - 1) * NN + s * N + c);
+            pre = c >= s ? x.re : -x.im;  // P[s][c]
+            pre2 = c > s ? x.im : x.re;   // P[c][s]
+        }
+    } else {
+        has_pre = tid < 2 * nrn && sMnb[(tid < nrn ? tid : tid - nrn) / N] >= 0;
+        if (has_pre) {
+            const int x = tid < nrn ? tid : tid - nrn;
+            const int a = x / N, c = x - (x / N) * N, s = sMsite[a];
+            pre = tid < nrn ? pk_nb(nbs, sMnb[a], s, c) : pk_nb(nbs, sMnb[a], c, s);
+        }
+    }
+    {
+        const T* plane = half ? sSim : sSre;
+        T* out = half ? sXim : sXre;
+        acc_t acc[NB];
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) acc[cb] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            T bval[NB];
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb)
+                bval[cb] = plane[(4 * ks + (lane >> 4)) * LS + 16 * cb + (lane & 15)];
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb) acc[cb] = mfma16(hreg[ks], bval[cb], acc[cb]);
+        }
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                out[(16 * mt + mfma_row<T>(lane, r)) * LX + 16 * cb + (lane & 15)] = acc[cb][r];
+    }
+    if (has_pre) {
+        sRow[tid] = pre;
+        if (mir_in) sCol[tid] = pre2;
+    }
+    __syncthreads();  // sigma planes are free from here on
+
+    // 3. "+" neighbours at the thread's own elements: modes of state i, then of j.
+    T xp[EPT][2 * KP];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k)
+#pragma unroll
+        for (int q = 0; q < 2 * KP; ++q) xp[k][q] = (T)0;
+    if (has_plus && jin) {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int i = r0 + RS * k;
+            if (i < N && i != j) {
+#pragma unroll
+                for (int q = 0; q < 2 * KP; ++q) {
+                    const int s = q < KP ? i : j, qq = q < KP ? q : q - KP;
+                    const int m0 = sBegin[s];
+                    if (qq < sBegin[s + 1] - m0) xp[k][q] = G(sPptr[sModes[m0 + qq]])[i * N + j];
+                }
+            }
+        }
+    }
+    // 4. Q[i][j] = (sum over modes of i - sum over modes of j) w_l P_{u+e_l}[i][j],
+    //    read by element (j, i); the stage bases in flight.
+    T* sQ = sSre;
+    if (has_plus && jin) {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int i = r0 + RS * k;
+            if (i >= N || i == j) continue;
+            T q = 0;
+#pragma unroll
+            for (int pass = 0; pass < 2; ++pass) {
+                const int s = pass == 0 ? i : j;
+                const int m0 = sBegin[s], cnt = sBegin[s + 1] - m0;
+                T acc = 0;
+#pragma unroll
+                for (int qq = 0; qq < KP; ++qq)
+                    if (qq < cnt) acc += sPa[sModes[m0 + qq]] * xp[k][pass * KP + qq];
+                for (int qq = KP; qq < cnt; ++qq) {
+                    const int l = sModes[m0 + qq];
+                    acc += sPa[l] * G(sPptr[l])[i * N + j];
+                }
+                q += pass == 0 ? acc : -acc;
+            }
+            sQ[i * LX + j] = q;
+        }
+    }
+    T bv[NBASE][EPT];
+#pragma unroll
+    for (int m = 0; m < NBASE; ++m) {
+        if (m < sp.nbase) {
+#pragma unroll
+            for (int k = 0; k < EPT; ++k) {
+                const int i = r0 + RS * k;
+                bv[m][k] = G(bptr[m])[min(i, N - 1) * N + jc];  // unused outside N x N
+            }
+        }
+    }
+    uint64_t mmask = 0;
+#pragma unroll
+    for (int a = 0; a < kPrefRows; ++a)
+        if (lsite[a] >= 0) mmask |= 1ull << lsite[a];
+    for (int a = kPrefRows; a < Dm; ++a) {
+        const int s = uniform(sMsite[a]);
+        if (s >= 0) mmask |= 1ull << s;
+    }
+    __syncthreads();
+
+    // 5. Elementwise right-hand side in P-space and the stage combination.
+    const T h = (T)(sp.hmul * J.dt), w_in = (T)sp.w_in;
+    T* outp = reinterpret_cast<T*>(J.rest[sp.out]) + (size_t)(u - 1) * NN;
+    const T dj = sDelta[j < N ? j : 0];
+    const bool row_j = (mmask >> j) & 1;
+    T yv[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int i = r0 + RS * k;
+        yv[k] = 0;
+        if (!jin || i >= N) continue;
+        const T p = cur[k];
+        T f;
+        if (i == j) {
+            f = 2 * sXim[i * LX + i] - gam * p;
+        } else {
+            f = i < j ? sXim[i * LX + j] + sXim[j * LX + i] : sXre[i * LX + j] - sXre[j * LX + i];
+            f -= (gam + sDelta[i] + dj) * p;
+            if (has_plus) f += sQ[j * LX + i];
+        }
+        if (((mmask >> i) & 1) || row_j) {
+            // "-" link a of state s, with P_{u-e_a}[i][j] = pij and [j][i] = pji
+            auto minus = [&](int a, int s, T ml, T mc) {
+                if (s != i && s != j) return;
+                T pij, pji;
+                if (a < n_rows) {
+                    pij = s == i ? sRow[a * N + j] : sCol[a * N + i];
+                    pji = s == i ? sCol[a * N + j] : sRow[a * N + i];
+                } else {
+                    pij = pk_nb(nbs, sMnb[a], i, j);
+                    pji = pk_nb(nbs, sMnb[a], j, i);
+                }
+                if (i == j)
+                    f += 2 * ml * pij;
+                else
+                    f += ml * pij + (s == j ? mc : -mc) * pji;
+            };
+#pragma unroll
+            for (int a = 0; a < kPrefRows; ++a)
+                if (lsite[a] >= 0) minus(a, lsite[a], lml[a], lmc[a]);
+            for (int a = kPrefRows; a < Dm; ++a)
+                if (sMsite[a] >= 0) minus(a, sMsite[a], sMml[a], sMmc[a]);
+        }
+        T y = w_in * p + h * f;
+#pragma unroll
+        for (int m = 0; m < NBASE; ++m)
+            if (m < sp.nbase) y += (T)sp.wbase[m] * bv[m][k];
+        G(outp)[i * N + j] = y;
+        yv[k] = y;
+    }
+    // 6. The complex copy of a lower-level output (the next stage's "-"
+    //    rows): P_out[j][i] from a transposed LDS read.  Workgroup-uniform
+    //    test (its ADOs are u0 and u0 + 1), so that every thread reaches the
+    //    barrier.
+    const int u0 = 1 + xcd_remap(blockIdx.x - s0_blocks, gridDim.x - s0_blocks) * AW;
+    if (sp.mirror_out && u0 <= J.n_low) {
+        T* sY = sSim;  // free since the matrix-core phase
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int i = r0 + RS * k;
+            if (jin && i < N) sY[i * LX + j] = yv[k];
+        }
+        __syncthreads();
+        if (jin && u <= J.n_low) {
+            void* mir_out = J.mirror[sp.mirror_out - 1];
+#pragma unroll
+            for (int k = 0; k < EPT; ++k) {
+                const int i = r0 + RS * k;
+                if (i >= N) continue;
+                const T yt = sY[j * LX + i];
+                const cpx<T> v = i <= j ? cpx<T>{yv[k], i < j ? yt : (T)0} : cpx<T>{yt, -yv[k]};
+                st<T>(mir_out, (size_t)(u - 1) * NN + i * N + j, v);
+            }
+        }
+    }
+}
+
+// Complex64 copy of packed ADOs: M[u][i][j] = sigma_u(i, j), u < n.
+__global__ __launch_bounds__(256) void k_pk_mirror(const float* P, void* M, int N, int64_t total) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    const int NN = N * N;
+    const int64_t u = idx / NN;
+    const int e = (int)(idx - u * NN), i = e / N, j = e - (e / N) * N;
+    const float* p = P + u * NN;
+    const float x = G(p)[min(i, j) * N + max(i, j)], y = G(p)[max(i, j) * N + min(i, j)];
+    st<float>(M, (size_t)idx, cpx<float>{x, i < j ? y : (i > j ? -y : 0.0f)});
+}
+
 }  // namespace
 
 int bulk_mfma_blocks(int N, bool h_complex, int precision) {
@@ -1157,6 +1531,14 @@ int bulk_ados_per_tile(int N, int W, int D, int tsize) {
     return g;
 }
 
+hipError_t launch_pk_mirror(const void* packed_rest, void* mirror, int N, int n, hipStream_t stream) {
+    const int64_t total = (int64_t)n * N * N;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pk_mirror, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream,
+                       static_cast<const float*>(packed_rest), mirror, N, total);
+    return hipGetLastError();
+}
+
 hipError_t launch_enumerate(const Tables& t, hipStream_t stream) {
     if (t.n_ado <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_enumerate, dim3((t.n_ado + 255) / 256), dim3(256), 0, stream, t);
@@ -1171,17 +1553,17 @@ hipError_t launch_enumerate(const Tables& t, hipStream_t stream) {
     return hipGetLastError();
 }
 
-template <typename T, bool BATCHED>
+template <typename T, bool BATCHED, bool PK = false>
 static hipError_t launch_sigma0_t(const Job& single, const Job* jobs_dev, int n_jobs,
                                   const StageSpec& sp, size_t lds, hipStream_t stream) {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sigma0<T, BATCHED>),
+        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sigma0<T, BATCHED, PK>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (a != hipSuccess) return a;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_sigma0<T, BATCHED>), dim3(BATCHED ? n_jobs : 1), dim3(kBlock), lds,
+    hipLaunchKernelGGL((k_sigma0<T, BATCHED, PK>), dim3(BATCHED ? n_jobs : 1), dim3(kBlock), lds,
                        stream, single, jobs_dev, n_jobs, sp, (unsigned)lds);
     return hipGetLastError();
 }
@@ -1191,7 +1573,7 @@ static hipError_t launch_sigma0_t(const Job& single, const Job* jobs_dev, int n_
 // launch's LDS, which may grow up to `lds_budget` (what costs the bulk
 // kernel no occupancy); otherwise it gets its own launch first.  Sets the
 // number of workgroups to add and the launch's LDS.
-template <typename T, bool BATCHED>
+template <typename T, bool BATCHED, bool PK = false>
 static hipError_t sigma0_ride_along(const Job& single, const Job* jobs_dev, int n_jobs, int n_s0,
                                     bool allow, const StageSpec& sp, size_t lds_budget,
                                     hipStream_t stream, int* added, size_t* lds) {
@@ -1207,7 +1589,7 @@ static hipError_t sigma0_ride_along(const Job& single, const Job* jobs_dev, int 
         return hipSuccess;
     }
     const size_t lds0 = sigma0_lds(N, W, (int)sizeof(T), false, 160 * 1024).total;
-    return launch_sigma0_t<T, BATCHED>(single, jobs_dev, n_jobs, sp, lds0, stream);
+    return launch_sigma0_t<T, BATCHED, PK>(single, jobs_dev, n_jobs, sp, lds0, stream);
 }
 
 template <typename T, int NB, bool HERM, bool BATCHED, int NBASE>
@@ -1280,6 +1662,38 @@ static hipError_t launch_mfma(int nb, bool herm, const Job& single, const Job* j
 }
 
 
+template <int NB, int NBASE>
+static hipError_t launch_mfma_pk_t(const Job& single, int total_tiles, const StageSpec& sp,
+                                   hipStream_t stream) {
+    const void* fn = reinterpret_cast<const void*>(&k_bulk_mfma_pk<NB, NBASE>);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t a =
+            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (a != hipSuccess) return a;
+        attr_set = true;
+    }
+    constexpr int AW = mfma_ados_per_wg<float, NB>();
+    const unsigned stride =
+        (unsigned)((MfmaLds<float, NB, true>::bytes(single.t.N, single.t.W, single.t.D) + 15) & ~(size_t)15);
+    size_t lds = (size_t)stride * AW;
+    int extra = 0;
+    hipError_t e = sigma0_ride_along<float, false, true>(single, nullptr, 1, 1, true, sp, lds, stream,
+                                                         &extra, &lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_bulk_mfma_pk<NB, NBASE>), dim3(extra + (total_tiles + AW - 1) / AW),
+                       dim3(128 * NB * AW), lds, stream, single, sp, total_tiles, stride, extra,
+                       (unsigned)lds);
+    return hipGetLastError();
+}
+
+template <int NB>
+static hipError_t launch_mfma_pk_nb(const Job& single, int total_tiles, const StageSpec& sp,
+                                    hipStream_t stream) {
+    if (sp.nbase <= 1) return launch_mfma_pk_t<NB, 1>(single, total_tiles, sp, stream);
+    return launch_mfma_pk_t<NB, 3>(single, total_tiles, sp, stream);
+}
+
 template <typename T, bool BATCHED, bool HC>
 static hipError_t launch_fma_t(const Job& single, const Job* jobs_dev, int n_jobs,
                                int total_tiles, const StageSpec& sp, size_t lds,
@@ -1349,12 +1763,44 @@ static hipError_t launch_stage_t(const Job& single, const Job* jobs_dev, int n_j
     return e;
 }
 
+// Hermitian-packed FP32 storage: single jobs on the matrix-core path only.
+static hipError_t launch_stage_pk(const Job& single, int total_tiles, const StageSpec& sp,
+                                  hipStream_t stream, hipEvent_t ev_begin, hipEvent_t ev_end) {
+    const int N = single.t.N;
+    hipError_t e;
+    if (total_tiles == 0) {
+        const size_t lds0 = sigma0_lds(N, single.t.W, 4, false, 160 * 1024).total;
+        e = launch_sigma0_t<float, false, true>(single, nullptr, 1, sp, lds0, stream);
+        if (e != hipSuccess) g_launch_what = "sigma_0 stage kernel";
+        return e;
+    }
+    const int nb = bulk_mfma_blocks(N, single.t.h_complex != 0, 2);
+    if (nb < 1 || nb > 4) return hipErrorInvalidValue;
+    if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
+    switch (nb) {
+        case 1: e = launch_mfma_pk_nb<1>(single, total_tiles, sp, stream); break;
+        case 2: e = launch_mfma_pk_nb<2>(single, total_tiles, sp, stream); break;
+        case 3: e = launch_mfma_pk_nb<3>(single, total_tiles, sp, stream); break;
+        default: e = launch_mfma_pk_nb<4>(single, total_tiles, sp, stream); break;
+    }
+    if (e != hipSuccess) {
+        g_launch_what = "packed MFMA bulk stage kernel";
+        return e;
+    }
+    if (ev_end) e = hipEventRecord(ev_end, stream);
+    return e;
+}
+
 const char* last_launch_failure() { return g_launch_what; }
 
 hipError_t launch_stage(const Job& single, const Job* jobs_dev, int n_jobs, int total_tiles,
                         int precision, const StageSpec& sp, hipStream_t stream,
                         hipEvent_t ev_begin, hipEvent_t ev_end) {
     g_launch_what = "";
+    if (precision == 2) {
+        if (jobs_dev != nullptr) return hipErrorInvalidValue;
+        return launch_stage_pk(single, total_tiles, sp, stream, ev_begin, ev_end);
+    }
     if (precision == 0)
         return launch_stage_t<double>(single, jobs_dev, n_jobs, total_tiles, sp, stream,
                                       ev_begin, ev_end);

@@ -519,6 +519,8 @@ heom_status heom_server_create(void* arena_dev, size_t arena_bytes, int32_t max_
 
 heom_status heom_submit(heom_server* s, const heom_request* q, uint64_t* ticket) {
     if (!s || !q || !ticket) return srv_fail(HEOM_E_INVAL, "NULL argument");
+    if (q->problem.precision == HEOM_FP32_HERM)
+        return srv_fail(HEOM_E_INVAL, "the server takes HEOM_FP64 and HEOM_FP32_MIXED requests");
     heom_info info;
     heom_status st = heom_plan(&q->problem, &info);
     if (st != HEOM_OK) return srv_fail(st, heom_last_error());

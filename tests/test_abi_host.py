@@ -150,3 +150,37 @@ def test_bulk_kernel_choice(heom):
     cplx["H"][0, 1] += 1j
     cplx["H"][1, 0] -= 1j
     assert heom.plan(cplx, heom.FP32_MIXED)["bulk_kernel"] == 0
+
+
+def test_fp32_herm_plan(heom):
+    # Hermitian-packed storage: N^2 reals per ADO, matrix-core path only
+    from paper_1803_03498_amd._abi import HeomError
+    for prob in (hi.aggregate24(), hi.aggregate48()):
+        info = heom.plan(prob, heom.FP32_HERM)
+        N = prob["H"].shape[0]
+        assert info["elem_bytes"] == 4
+        assert info["rest_bytes"] == (info["n_ado"] - 1) * N * N * 4
+        assert info["sigma0_bytes"] == N * N * 16
+        assert info["bulk_kernel"] == 1
+    big = _bad(hi.dimer(), H=np.eye(64), baths=[])
+    assert heom.plan(big, heom.FP32_HERM)["elem_bytes"] == 4
+    cplx = _bad(hi.aggregate24(), H=hi.aggregate24()["H"] * (1 + 0j))
+    cplx["H"][0, 1] += 1j
+    cplx["H"][1, 0] -= 1j
+    for prob in (hi.fmo_like(), hi.dimer(), cplx):
+        with pytest.raises(HeomError) as ei:
+            heom.plan(prob, heom.FP32_HERM)
+        assert ei.value.status == -1
+
+
+def test_pack_hermitian_layout(heom):
+    rng = np.random.default_rng(11)
+    x = rng.normal(size=(4, 6, 6)) + 1j * rng.normal(size=(4, 6, 6))
+    x = (x + np.conj(np.swapaxes(x, 1, 2))) / 2
+    P = heom.pack_hermitian(x)
+    assert P.shape == x.shape and P.dtype == np.float64
+    for i in range(6):
+        for j in range(6):
+            want = x[:, i, j].real if i <= j else x[:, j, i].imag
+            assert np.array_equal(P[:, i, j], want)
+    assert np.array_equal(heom.unpack_hermitian(P), x)

@@ -144,6 +144,67 @@ def test_rhs_fp32_mixed(heom, orc, case, herm):
     assert np.max(np.abs(got - ref)) <= 1e-5 * scale
 
 
+# Hermitian-packed FP32 storage: real H, N >= 16 (the matrix-core path)
+PK_CASES = [c for c in RHS_CASES if c[1] >= 16 and not c[5]]
+
+
+@pytest.mark.parametrize("case", PK_CASES, ids=[f"N{c[1]}_B{c[2]}_M{c[3]}_D{c[4]}_{c[0]}"
+                                                for c in PK_CASES])
+def test_rhs_fp32_herm(heom, orc, case):
+    seed, N, nb, M, D, extra = case
+    _print_case("rhs fp32 packed", case)
+    prob = _rhs_problem(seed, N, nb, M, D, extra)
+    h = heom.Hierarchy(prob, heom.FP32_HERM)
+    x = hi.random_state(300 + seed, h.n_ado, N, hermitian=True)
+    # the oracle sees the same FP32 inputs
+    x[1:] = heom.unpack_hermitian(heom.pack_hermitian(x[1:]).astype(np.float32))
+    ref = orc.rhs(prob, x)
+    out = h.new_state()
+    assert out[1].dtype.itemsize == 4
+    h.rhs(h.state_from_numpy(x), out, hermitian=True)
+    got = h.state_to_numpy(out)
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(got[0] - ref[0])) <= 1e-6 * scale
+    assert np.max(np.abs(got - ref)) <= 1e-5 * scale
+
+
+@pytest.mark.parametrize("case", [c for c in PK_CASES if c[0] in (8, 11, 22, 24, 25)],
+                         ids=lambda c: f"N{c[1]}_D{c[4]}_{c[0]}")
+def test_propagate_fp32_herm_matches_fp32_mixed(heom, case):
+    # propagation keeps complex copies of the lower levels for the "-" rows;
+    # the packed run must track the complex FP32 run on every ADO
+    seed, N, nb, M, D, extra = case
+    _print_case("propagate fp32 packed vs complex", case)
+    prob = _rhs_problem(seed, N, nb, M, D, extra)
+    finals = []
+    for prec in (heom.FP32_MIXED, heom.FP32_HERM):
+        h = heom.Hierarchy(prob, prec)
+        x = hi.random_state(400 + seed, h.n_ado, N, hermitian=True, scale=0.05)
+        x[0] = np.eye(N) / N
+        x[1:] = heom.unpack_hermitian(heom.pack_hermitian(x[1:]).astype(np.float32))
+        st = h.state_from_numpy(x)
+        rec = h.propagate(st, 0.25, 12, 3, hermitian=True)
+        assert np.all(np.isfinite(rec))
+        finals.append(h.state_to_numpy(st))
+    scale = np.max(np.abs(finals[0]))
+    assert np.max(np.abs(finals[0] - finals[1])) <= 1e-5 * scale
+
+
+def test_fp32_herm_rejections(heom):
+    from paper_1803_03498_amd._abi import HeomError
+    prob = hi.aggregate24(n_steps=4)
+    h = heom.Hierarchy(prob, heom.FP32_HERM)
+    st = h.new_state(prob["rho0"])
+    out = h.new_state()
+    with pytest.raises(HeomError):
+        h.rhs(st, out, hermitian=False)
+    with pytest.raises(HeomError):
+        h.propagate(st, 1.0, 2, 1, hermitian=False)
+    srv = heom.Server(1 << 28, 2)
+    with pytest.raises(HeomError, match="server takes"):
+        srv.submit(hi.serving_mix(1, seed=3)[0]["runs"], precision=heom.FP32_HERM)
+
+
 # ----------------------------------------------------------- propagation ----
 
 def test_propagate_fp64_dimer_full(heom, orc):

@@ -5,7 +5,8 @@
 * FMO-like linear absorption (3 directions, 1 ps): dipole correlation and the
   spectrum within 1e-4 relative.
 * 24-site (20475 ADOs) and 48-site (156849 ADOs) aggregates: the right-hand
-  side in the launch configuration the benchmark times, compared with the
+  side in the launch configurations the benchmark times (FP64, FP32-mixed and
+  Hermitian-packed FP32), compared with the
   oracle on sampled ADOs from every level (the oracle evaluates them one by
   one; every other ADO is zero except the neighbours of the sampled ones).
 """
@@ -100,19 +101,27 @@ def _sampled_rhs(heom, orc, prob, precision, width, seed):
     rng = np.random.default_rng(seed)
     vals = rng.normal(size=(len(need), N, N)) + 1j * rng.normal(size=(len(need), N, N))
     vals = (vals + np.conj(np.transpose(vals, (0, 2, 1)))) / 2  # Hermitian ADOs
-    vals[need > 0] = vals[need > 0].astype(np.complex128 if precision == 0 else np.complex64)
+    if precision == heom.FP32_HERM:
+        vals[need > 0] = heom.unpack_hermitian(heom.pack_hermitian(vals[need > 0]).astype(np.float32))
+    else:
+        vals[need > 0] = vals[need > 0].astype(np.complex128 if precision == 0 else np.complex64)
     # oracle input: zero except the needed ADOs (pages of the rest stay untouched)
     x = np.zeros((n, N, N), np.complex128)
     x[need] = vals
     h = heom.Hierarchy(prob, precision)
     s0, rest = h.new_state(vals[0])
     idx = torch.as_tensor(need[need > 0] - 1, device="cuda")
-    rest.index_copy_(0, idx, torch.as_tensor(vals[need > 0]).to(rest.dtype).cuda())
+    src = vals[need > 0]
+    if precision == heom.FP32_HERM:
+        src = heom.pack_hermitian(src)
+    rest.index_copy_(0, idx, torch.as_tensor(src).to(rest.dtype).cuda())
     out = h.new_state()
     h.rhs((s0, rest), out, hermitian=True)
     torch.cuda.synchronize()
     del rest
     got_rest = out[1][torch.as_tensor(sample - 1, device="cuda")].cpu().numpy()
+    if precision == heom.FP32_HERM:
+        got_rest = heom.unpack_hermitian(got_rest)
     ref = np.zeros((len(sample), N, N), np.complex128)
     pos = {u: k for k, u in enumerate(sample)}
     for a, b in ranges:
@@ -123,14 +132,14 @@ def _sampled_rhs(heom, orc, prob, precision, width, seed):
     return got_rest, ref
 
 
-@pytest.mark.parametrize("precision,tol", [(1, 1e-5), (0, 1e-12)])
+@pytest.mark.parametrize("precision,tol", [(1, 1e-5), (0, 1e-12), (2, 1e-5)])
 def test_aggregate24_rhs_sampled(heom, orc, precision, tol):
     _case("aggregate24 sampled rhs", precision)
     got, ref = _sampled_rhs(heom, orc, hi.aggregate24(), precision, 40, 24)
     assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("precision,tol", [(1, 1e-5), (0, 1e-12)])
+@pytest.mark.parametrize("precision,tol", [(1, 1e-5), (0, 1e-12), (2, 1e-5)])
 def test_aggregate48_rhs_sampled(heom, orc, precision, tol):
     _case("aggregate48 sampled rhs", precision)
     got, ref = _sampled_rhs(heom, orc, hi.aggregate48(), precision, 12, 48)
@@ -138,12 +147,15 @@ def test_aggregate48_rhs_sampled(heom, orc, precision, tol):
 
 
 def test_aggregate24_fp32_tracks_fp64(heom):
-    _case("aggregate24 fp32 vs fp64 100 steps")
+    _case("aggregate24 fp32 and fp32 packed vs fp64 100 steps")
     prob = hi.aggregate24(n_steps=100)
     recs = []
-    for precision in (0, 1):
+    for precision in (0, 1, 2):
         h = heom.Hierarchy(prob, precision)
         st = h.new_state(prob["rho0"])
         recs.append(h.propagate(st, 1.0, 100, 10, hermitian=True))
         del st, h
     assert np.max(np.abs(recs[0][:, :24] - recs[1][:, :24])) <= 1e-5
+    # Hermitian-packed storage: the same FP32 arithmetic on half the bytes
+    assert np.max(np.abs(recs[0][:, :24] - recs[2][:, :24])) <= 1e-5
+    assert np.max(np.abs(recs[2][:, 24] - 1.0)) <= 1e-12   # FP64 trace
