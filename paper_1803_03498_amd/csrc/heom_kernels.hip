@@ -248,6 +248,13 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return x * per + (x < rem ? x : rem) + idx;
 }
 
+// As xcd_remap, but the first n_first workgroups (those holding ADOs below
+// the top level, which carry the "+" couplings and cost more) keep their
+// order and so are spread round-robin over all XCDs instead of loading one.
+__device__ __forceinline__ int xcd_remap_low(int b, int nb, int n_first) {
+    return b < n_first ? b : n_first + xcd_remap(b - n_first, nb - n_first);
+}
+
 // The job a tile belongs to.  Single-job launches read the descriptor from
 // the kernel argument; batched launches from the device job table (found by
 // binary search over the jobs' first tiles).  Keeping the two apart lets the
@@ -828,7 +835,8 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute
     const int tid = (int)threadIdx.x - sub * NT;
     const int lane = tid & 63, wave = tid >> 6;
     const int mt = wave >> 1, half = wave & 1;
-    const int tile = xcd_remap(blockIdx.x - s0_blocks, gridDim.x - s0_blocks) * AW + sub;
+    const int n_first = BATCHED ? 0 : min((single.n_low + AW - 1) / AW, (int)gridDim.x - s0_blocks);
+    const int tile = xcd_remap_low(blockIdx.x - s0_blocks, gridDim.x - s0_blocks, n_first) * AW + sub;
     // A half without an ADO still takes part in every barrier.
     const bool active = tile < total_tiles;
     const Job& J = JobOf<BATCHED>::get(single, jobs, n_jobs, active ? tile : total_tiles - 1);
@@ -1212,7 +1220,8 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<float, NB>())) __attri
     const int tid = (int)threadIdx.x - sub * NT;
     const int lane = tid & 63, wave = tid >> 6;
     const int mt = wave >> 1, half = wave & 1;
-    const int tile = xcd_remap(blockIdx.x - s0_blocks, gridDim.x - s0_blocks) * AW + sub;
+    const int n_first = min((single.n_low + AW - 1) / AW, (int)gridDim.x - s0_blocks);
+    const int tile = xcd_remap_low(blockIdx.x - s0_blocks, gridDim.x - s0_blocks, n_first) * AW + sub;
     const bool active = tile < total_tiles;
     const Job& J = single;
     const Tables& t = J.t;
@@ -1420,9 +1429,31 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<float, NB>())) __attri
 #pragma unroll
     for (int a = 0; a < kPrefRows; ++a)
         if (lsite[a] >= 0) mmask |= 1ull << lsite[a];
+    // "-" links past the staged rows (depth > kPrefRows): their terms here,
+    // so that the elementwise phase issues no global loads (a wait for
+    // those would also wait for its own stores).
+    T fl[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) fl[k] = (T)0;
     for (int a = kPrefRows; a < Dm; ++a) {
         const int s = uniform(sMsite[a]);
-        if (s >= 0) mmask |= 1ull << s;
+        if (s < 0) continue;
+        mmask |= 1ull << s;
+        if (!jin) continue;
+        const T ml = sMml[a], mc = sMmc[a];
+        const int nb = sMnb[a];
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+            const int i = r0 + RS * k;
+            if (i >= N || (s != i && s != j)) continue;
+            const T pij = pk_nb(nbs, nb, i, j);
+            if (i == j) {
+                fl[k] += 2 * ml * pij;
+            } else {
+                const T pji = pk_nb(nbs, nb, j, i);
+                fl[k] += ml * pij + (s == j ? mc : -mc) * pji;
+            }
+        }
     }
     __syncthreads();
 
@@ -1447,27 +1478,20 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<float, NB>())) __attri
             if (has_plus) f += sQ[j * LX + i];
         }
         if (((mmask >> i) & 1) || row_j) {
-            // "-" link a of state s, with P_{u-e_a}[i][j] = pij and [j][i] = pji
-            auto minus = [&](int a, int s, T ml, T mc) {
-                if (s != i && s != j) return;
-                T pij, pji;
-                if (a < n_rows) {
-                    pij = s == i ? sRow[a * N + j] : sCol[a * N + i];
-                    pji = s == i ? sCol[a * N + j] : sRow[a * N + i];
-                } else {
-                    pij = pk_nb(nbs, sMnb[a], i, j);
-                    pji = pk_nb(nbs, sMnb[a], j, i);
-                }
-                if (i == j)
-                    f += 2 * ml * pij;
-                else
-                    f += ml * pij + (s == j ? mc : -mc) * pji;
-            };
+            // staged "-" link a (a < n_rows) of state s, with
+            // P_{u-e_a}[i][j] = pij and P_{u-e_a}[j][i] = pji
 #pragma unroll
-            for (int a = 0; a < kPrefRows; ++a)
-                if (lsite[a] >= 0) minus(a, lsite[a], lml[a], lmc[a]);
-            for (int a = kPrefRows; a < Dm; ++a)
-                if (sMsite[a] >= 0) minus(a, sMsite[a], sMml[a], sMmc[a]);
+            for (int a = 0; a < kPrefRows; ++a) {
+                const int s = lsite[a];
+                if (s < 0 || (s != i && s != j)) continue;
+                const T pij = s == i ? sRow[a * N + j] : sCol[a * N + i];
+                const T pji = s == i ? sCol[a * N + j] : sRow[a * N + i];
+                if (i == j)
+                    f += 2 * lml[a] * pij;
+                else
+                    f += lml[a] * pij + (s == j ? lmc[a] : -lmc[a]) * pji;
+            }
+            f += fl[k];
         }
         T y = w_in * p + h * f;
 #pragma unroll
@@ -1480,7 +1504,7 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<float, NB>())) __attri
     //    rows): P_out[j][i] from a transposed LDS read.  Workgroup-uniform
     //    test (its ADOs are u0 and u0 + 1), so that every thread reaches the
     //    barrier.
-    const int u0 = 1 + xcd_remap(blockIdx.x - s0_blocks, gridDim.x - s0_blocks) * AW;
+    const int u0 = 1 + xcd_remap_low(blockIdx.x - s0_blocks, gridDim.x - s0_blocks, n_first) * AW;
     if (sp.mirror_out && u0 <= J.n_low) {
         T* sY = sSim;  // free since the matrix-core phase
 #pragma unroll
