@@ -35,6 +35,7 @@ FLAG_NO_RESCALE = 1
 FLAG_NO_TERMINATOR = 2
 FLAG_ADD_REORG = 4
 FLAG_STANDARD_GAUGE = 8
+FLAG_PADE = 16
 
 
 def _baths(n_sites, lam, tau, M, first_state=0):
@@ -154,6 +155,18 @@ def fmo_like(n_steps=2000, seed=7):
     return {"name": "fmo_like", "H": H, "baths": _baths(7, 35.0, 50.0, 1), "temperature_K": 300.0,
             "depth": 4, "flags": 0, "dt_fs": 1.0, "n_steps": n_steps, "record_every": 1,
             "rho0": population_rho0(7), "observable": {"kind": "population"}}
+
+
+def fmo_like_pade(T=77.0, depth=3, poles=1, n_steps=200, dt_fs=1.0, seed=7):
+    """The fmo_like system at temperature T with the Pade expansion of the
+    paper's low-temperature settings: (D, K) = (3, 2) at 77 K and (3, 4) at
+    30 K, K counting the k = 0 mode, i.e. K - 1 Pade poles per bath."""
+    rng = np.random.default_rng(seed)
+    H = fmo_like_hamiltonian(rng, 7)
+    return {"name": "fmo_like_pade", "H": H, "baths": _baths(7, 35.0, 50.0, poles),
+            "temperature_K": T, "depth": depth, "flags": FLAG_PADE, "dt_fs": dt_fs,
+            "n_steps": n_steps, "record_every": 1, "rho0": population_rho0(7),
+            "observable": {"kind": "population"}}
 
 
 def fmo_like_absorption(n_steps=1000, seed=7, dipole_seed=70):

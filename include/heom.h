@@ -67,14 +67,20 @@ enum {
                              16 <= N <= 64); not accepted by heom_submit.           */
 };
 
-/* Test switches (heom_problem.flags).  Both the library and the oracle honour them. */
+/* Switches (heom_problem.flags).  Both the library and the oracle honour them. */
 enum {
     HEOM_FLAG_NO_RESCALE = 1u,     /* plain couplings i V^x and n theta instead of the
                                       rescaled ones (substitution of section "HEOM
                                       formalism") */
     HEOM_FLAG_NO_TERMINATOR = 2u,  /* drop the third line of eq. HEOM                  */
     HEOM_FLAG_ADD_REORG = 4u,      /* add lambda_b to H[s_b][s_b] (eq. h-ex)           */
-    HEOM_FLAG_STANDARD_GAUGE = 8u  /* flip the sign of both coupling lines             */
+    HEOM_FLAG_STANDARD_GAUGE = 8u, /* flip the sign of both coupling lines             */
+    HEOM_FLAG_PADE = 16u           /* Pade expansion of the Bose function (section "HEOM
+                                      formalism", the replacement of the Matsubara
+                                      expansion): each bath's n_matsubara counts Pade
+                                      poles K (1 + K modes, K <= 64), gamma(b,k) and
+                                      c(b,k) take their Pade forms.  The correction
+                                      coefficient Delta then vanishes up to rounding. */
 };
 
 /* Observables recorded from sigma_0 (FP64). */
@@ -89,7 +95,8 @@ enum {
  * projector |state><state| (section "Frenkel exciton model"). */
 typedef struct {
     int32_t state;        /* 0 <= state < n_states                        */
-    int32_t n_matsubara;  /* M >= 0: the bath contributes 1 + M modes     */
+    int32_t n_matsubara;  /* M >= 0: the bath contributes 1 + M modes (M Matsubara
+                             terms, or M Pade poles with HEOM_FLAG_PADE)  */
     double lambda_cm;     /* reorganisation energy lambda >= 0, cm^-1     */
     double tau_fs;        /* nu^-1 > 0, fs                                */
 } heom_bath;
@@ -182,6 +189,12 @@ heom_status heom_copy_tables(const heom_hierarchy* h, uint8_t* tuples, int32_t* 
  * coefficient summed per state, 1/fs).  Any pointer may be NULL. */
 heom_status heom_coefficients(const heom_hierarchy* h, double* gamma, double* c, double* lamnu,
                               double* delta_state);
+
+/* The same coefficients straight from a problem, on the host (no GPU, no
+ * hierarchy): validates the problem as heom_plan does; the arrays hold W
+ * (n_modes of heom_plan) and N entries.  Any pointer may be NULL. */
+heom_status heom_problem_coefficients(const heom_problem* problem, double* gamma, double* c,
+                                      double* lamnu, double* delta_state);
 
 /* One evaluation out = f(in) of eq. HEOM (with the rescaled couplings unless
  * HEOM_FLAG_NO_RESCALE) over every ADO.  in and out must not overlap.

@@ -66,13 +66,16 @@ def lib():
         L.orc_tables.argtypes = [i32, i32, i64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_void_p, P(i64)]
         L.orc_bath_coefficients.argtypes = [d, d, d, i32, P(d), P(d), P(d), P(d)]
+        L.orc_bath_coefficients_pade.argtypes = [d, d, d, i32, P(d), P(d), P(d), P(d)]
+        L.orc_pade_poles.argtypes = [i32, P(d), P(d)]
         L.orc_model_sizes.argtypes = [P(_Problem), P(i32), P(i64)]
         L.orc_rhs.argtypes = [P(_Problem), ctypes.c_void_p, ctypes.c_void_p, i64, i64]
         L.orc_propagate.argtypes = [P(_Problem), ctypes.c_void_p, d, i64, i32, i32,
                                     ctypes.c_void_p, i32, ctypes.c_void_p]
         L.orc_spectrum.argtypes = [ctypes.c_void_p, i32, i64, d, ctypes.c_void_p, i64,
                                    ctypes.c_void_p]
-        for f in ("orc_count", "orc_tables", "orc_bath_coefficients", "orc_model_sizes",
+        for f in ("orc_count", "orc_tables", "orc_bath_coefficients",
+                  "orc_bath_coefficients_pade", "orc_pade_poles", "orc_model_sizes",
                   "orc_rhs", "orc_propagate", "orc_spectrum"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -126,16 +129,25 @@ def tables(W, D):
     return t[:, :W], p[:, :W], m[:, :W], lev
 
 
-def bath_coefficients(lambda_cm, tau_fs, T, M):
-    """(gamma[M+1] 1/fs, c[M+1] rad/fs^2, lambda*nu, Delta) in hbar = 1 units."""
+def bath_coefficients(lambda_cm, tau_fs, T, M, pade=False):
+    """(gamma[M+1] 1/fs, c[M+1] rad/fs^2, lambda*nu, Delta) in hbar = 1 units;
+    M Matsubara terms, or M Pade poles with pade=True."""
     g = np.zeros(M + 1)
     c = np.zeros(M + 1)
     ln = ctypes.c_double()
     dl = ctypes.c_double()
-    if lib().orc_bath_coefficients(lambda_cm, tau_fs, T, M, _dptr(g), _dptr(c), ctypes.byref(ln),
-                                   ctypes.byref(dl)):
+    f = lib().orc_bath_coefficients_pade if pade else lib().orc_bath_coefficients
+    if f(lambda_cm, tau_fs, T, M, _dptr(g), _dptr(c), ctypes.byref(ln), ctypes.byref(dl)):
         raise ValueError("bad bath")
     return g, c, ln.value, dl.value
+
+
+def pade_poles(K):
+    """(xi[K], eta[K]): Pade poles and residues of the Bose function."""
+    xi, eta = np.zeros(K), np.zeros(K)
+    if lib().orc_pade_poles(K, _dptr(xi), _dptr(eta)):
+        raise ValueError("K < 1")
+    return xi, eta
 
 
 def sizes(prob):

@@ -1,8 +1,8 @@
 // HEOM oracle — TEST INFRASTRUCTURE ONLY.
 //
 // A plain, slow, single-threaded FP64 implementation of the hierarchical
-// equations of motion (HEOM) for Drude-Lorentz baths with a Matsubara
-// expansion, integrated with textbook classic RK4.  It exists to check the GPU
+// equations of motion (HEOM) for Drude-Lorentz baths with a Matsubara or a
+// Pade expansion, integrated with textbook classic RK4.  It exists to check the GPU
 // library against; nothing in the product links, loads or calls it.  Only the
 // test suite, the smoke check and the CPU-baseline leg of the benchmark may
 // load this library.  It shares no code, header or table with the GPU path.
@@ -47,6 +47,7 @@ enum : uint32_t {
     kNoTerminator = 2u,   // drop the low-temperature correction term
     kAddReorg = 4u,       // add lambda_b to the diagonal of H (eq. h-ex)
     kStandardGauge = 8u,  // flip the sign of both coupling terms
+    kPade = 16u,          // Pade poles in place of the Matsubara frequencies
 };
 
 struct Mode {
@@ -156,6 +157,108 @@ void build_tables(int W, int D, Model& m) {
     }
 }
 
+// Eigenvalues of the real symmetric n x n matrix A (row-major) by cyclic
+// Jacobi rotations, in descending order.
+std::vector<double> sym_eigenvalues(std::vector<double> A, int n) {
+    double total = 0.0;
+    for (double x : A) total += x * x;
+    for (int sweep = 0; sweep < 200; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off += A[p * n + q] * A[p * n + q];
+        if (off <= 1e-32 * total) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[p * n + q];
+                if (apq == 0.0) continue;
+                // rotation in the (p, q) plane that zeroes A[p][q]
+                const double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {  // A <- A J
+                    const double akp = A[k * n + p], akq = A[k * n + q];
+                    A[k * n + p] = c * akp - s * akq;
+                    A[k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {  // A <- J^T A
+                    const double apk = A[p * n + k], aqk = A[q * n + k];
+                    A[p * n + k] = c * apk - s * aqk;
+                    A[q * n + k] = s * apk + c * aqk;
+                }
+            }
+    }
+    std::vector<double> ev(n);
+    for (int i = 0; i < n; ++i) ev[i] = A[i * n + i];
+    std::sort(ev.begin(), ev.end(), [](double x, double y) { return x > y; });
+    return ev;
+}
+
+// Pade poles xi_i and residues eta_i, i = 1..K, of the Bose function, in the
+// form the paper takes from Hu, Xu and Yan (section "HEOM formalism", the
+// replacement of the Matsubara expansion): xi_i = 2 / (i-th largest
+// eigenvalue of Lambda), zeta_j = 2 / (j-th largest eigenvalue of Lambda'),
+//   eta_i = (K^2 + 3K/2) prod_{j<K} (zeta_j^2 - xi_i^2) / prod_{j != i} (xi_j^2 - xi_i^2).
+// Lambda (2K x 2K) and Lambda' (2K-1 x 2K-1) are zero on the diagonal with
+// 1/sqrt((2m+1)(2m+3)) and 1/sqrt((2m+3)(2m+5)) beside it, m = 1, 2, ...
+void pade_poles(int K, double* xi, double* eta) {
+    auto tridiag = [](int n, int shift) {
+        std::vector<double> A((size_t)n * n, 0.0);
+        for (int m = 1; m < n; ++m) {
+            const double v = 1.0 / std::sqrt((2.0 * m + shift) * (2.0 * m + shift + 2.0));
+            A[(size_t)(m - 1) * n + m] = v;
+            A[(size_t)m * n + m - 1] = v;
+        }
+        return A;
+    };
+    const std::vector<double> ev = sym_eigenvalues(tridiag(2 * K, 1), 2 * K);
+    const std::vector<double> evp = K > 1 ? sym_eigenvalues(tridiag(2 * K - 1, 3), 2 * K - 1)
+                                          : std::vector<double>();
+    std::vector<double> zeta(K > 1 ? K - 1 : 0);
+    for (int i = 0; i < K; ++i) xi[i] = 2.0 / ev[i];
+    for (int j = 0; j + 1 < K; ++j) zeta[j] = 2.0 / evp[j];
+    for (int i = 0; i < K; ++i) {
+        // the K-1 factors of the numerator and of the denominator taken in
+        // pairs, so that the partial products stay in range for large K
+        double r = K * K + 1.5 * K;
+        for (int j = 0, jd = 0; j + 1 < K; ++j, ++jd) {
+            if (jd == i) ++jd;
+            r *= (zeta[j] * zeta[j] - xi[i] * xi[i]) / (xi[jd] * xi[jd] - xi[i] * xi[i]);
+        }
+        eta[i] = r;
+    }
+}
+
+// Drude-Lorentz bath exponents and weights with the Pade expansion of K
+// poles (section "HEOM formalism", the Pade replacements of gamma(b,k) and
+// c(b,k); the sum in c(b,0) runs over the poles j) and the same correction
+// coefficient as below.  Returns -1 if a pole rate equals nu.
+int bath_coefficients_pade(double lambda_cm, double tau_fs, double T, int K, double* gamma,
+                           double* c, double* lamnu, double* delta) {
+    const double beta = 1.0 / (kBoltzmannCm * T * kTwoPiC);
+    const double lam = lambda_cm * kTwoPiC;
+    const double nu = 1.0 / tau_fs;
+    std::vector<double> xi(K), eta(K);
+    if (K > 0) pade_poles(K, xi.data(), eta.data());
+    double c0 = 1.0;
+    for (int j = 0; j < K; ++j) {
+        const double a = xi[j] / beta;
+        if (a == nu) return -1;
+        c0 -= 2.0 * eta[j] * nu * nu / (a * a - nu * nu);
+    }
+    gamma[0] = nu;
+    c[0] = 2.0 * lam / beta * c0;
+    double sum = c[0] / gamma[0];
+    for (int k = 1; k <= K; ++k) {
+        const double a = xi[k - 1] / beta;
+        gamma[k] = a;
+        c[k] = 4.0 * lam * nu / beta * eta[k - 1] * a / (a * a - nu * nu);
+        sum += c[k] / gamma[k];
+    }
+    *lamnu = lam * nu;
+    *delta = 2.0 * lam / (beta * nu) - sum;
+    return 0;
+}
+
 // Drude-Lorentz bath exponents and weights with the Matsubara expansion
 // (section "HEOM formalism", definitions of gamma(b,k) and c(b,k)) and the
 // low-temperature correction coefficient of the third line of eq. (HEOM).
@@ -200,8 +303,14 @@ int build_model(const orc_problem* p, Model& m) {
         if (!(p->bath_tau_fs[b] > 0.0) || !(p->bath_lambda_cm[b] >= 0.0)) return -1;
         std::vector<double> g(M + 1), c(M + 1);
         double lamnu = 0.0, delta = 0.0;
-        bath_coefficients(p->bath_lambda_cm[b], p->bath_tau_fs[b], p->temperature_K, M,
-                          g.data(), c.data(), &lamnu, &delta);
+        if (m.flags & kPade) {
+            if (bath_coefficients_pade(p->bath_lambda_cm[b], p->bath_tau_fs[b], p->temperature_K,
+                                       M, g.data(), c.data(), &lamnu, &delta))
+                return -1;
+        } else {
+            bath_coefficients(p->bath_lambda_cm[b], p->bath_tau_fs[b], p->temperature_K, M,
+                              g.data(), c.data(), &lamnu, &delta);
+        }
         for (int k = 0; k <= M; ++k)
             m.modes.push_back(Mode{b, k, s, g[k], c[k], k == 0 ? lamnu : 0.0});
         m.bath_site.push_back(s);
@@ -358,6 +467,20 @@ int orc_bath_coefficients(double lambda_cm, double tau_fs, double T_K, int32_t M
     if (M < 0 || !(T_K > 0.0) || !(tau_fs > 0.0)) return -1;
     bath_coefficients(lambda_cm, tau_fs, T_K, M, gamma, c, lamnu, delta);
     return 0;
+}
+
+// Pade poles and residues of the Bose function, K >= 1.
+int orc_pade_poles(int32_t K, double* xi, double* eta) {
+    if (K < 1) return -1;
+    pade_poles(K, xi, eta);
+    return 0;
+}
+
+// Coefficients of one bath with K Pade poles: gamma[0..K], c[0..K], lambda*nu, Delta.
+int orc_bath_coefficients_pade(double lambda_cm, double tau_fs, double T_K, int32_t K,
+                               double* gamma, double* c, double* lamnu, double* delta) {
+    if (K < 0 || !(T_K > 0.0) || !(tau_fs > 0.0)) return -1;
+    return bath_coefficients_pade(lambda_cm, tau_fs, T_K, K, gamma, c, lamnu, delta);
 }
 
 int orc_model_sizes(const orc_problem* p, int32_t* W, int64_t* n_ado) {

@@ -17,7 +17,7 @@ import numpy as np
 from . import _abi
 from ._abi import FP32_HERM, FP32_MIXED, FP64, OBS_DIPOLE, OBS_POPULATION, HeomError, check, load
 
-__all__ = ["FP64", "FP32_MIXED", "FP32_HERM", "pack_hermitian", "unpack_hermitian", "OBS_POPULATION", "OBS_DIPOLE", "HeomError", "Problem", "plan",
+__all__ = ["FP64", "FP32_MIXED", "FP32_HERM", "problem_coefficients", "pack_hermitian", "unpack_hermitian", "OBS_POPULATION", "OBS_DIPOLE", "HeomError", "Problem", "plan",
            "Hierarchy", "Server", "spectrum", "load"]
 
 
@@ -61,6 +61,19 @@ def plan(prob, precision=FP64):
     info = _abi.HeomInfo()
     check(load().heom_plan(ctypes.byref(p.struct), ctypes.byref(info)))
     return {f: getattr(info, f) for f, _ in _abi.HeomInfo._fields_}
+
+
+def problem_coefficients(prob):
+    """heom_problem_coefficients: (gamma [W], c [W], lambda*nu [W], Delta [N]) of a
+    problem, on the host (no GPU needed)."""
+    p = prob if isinstance(prob, Problem) else Problem(prob)
+    info = plan(p)
+    W, N = max(int(info["n_modes"]), 1), int(info["n_states"])
+    g, c, ln, ds = np.zeros(W), np.zeros(W), np.zeros(W), np.zeros(N)
+    check(load().heom_problem_coefficients(ctypes.byref(p.struct), g.ctypes.data, c.ctypes.data,
+                                           ln.ctypes.data, ds.ctypes.data))
+    n = int(info["n_modes"])
+    return g[:n], c[:n], ln[:n], ds
 
 
 def spectrum(P, dt_fs, omega_cm):

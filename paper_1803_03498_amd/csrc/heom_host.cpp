@@ -53,6 +53,69 @@ constexpr size_t mirror_bytes(int64_t n, int N) {
     return align256(std::max<size_t>((size_t)n * N * N * 8, 1));
 }
 
+constexpr int kMaxPade = 64;
+
+// Eigenvalues of the symmetric tridiagonal n x n matrix with zero diagonal
+// and off-diagonal e[0..n-2], in descending order: bisection on the Sturm
+// count (the number of negative pivots of T - x I is the number of
+// eigenvalues below x).
+std::vector<double> tridiag_eigenvalues_desc(const std::vector<double>& e, int n) {
+    double bound = 0.0;
+    for (double v : e) bound = std::max(bound, 2.0 * std::fabs(v));
+    bound += 1e-300;
+    auto below = [&](double x) {
+        int cnt = 0;
+        double q = -x;
+        for (int k = 0; k < n; ++k) {
+            if (k > 0) q = -x - e[k - 1] * e[k - 1] / q;
+            if (std::fabs(q) < 1e-300) q = -1e-300;  // a zero pivot counts as negative
+            if (q < 0.0) ++cnt;
+        }
+        return cnt;
+    };
+    std::vector<double> ev(n);
+    for (int j = 1; j <= n; ++j) {  // j-th smallest
+        double lo = -bound, hi = bound;
+        for (int it = 0; it < 200 && hi - lo > 1e-17 * std::max(1.0, std::fabs(lo)); ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (below(mid) >= j)
+                hi = mid;
+            else
+                lo = mid;
+        }
+        ev[n - j] = 0.5 * (lo + hi);
+    }
+    return ev;
+}
+
+// Pade poles xi_i and residues eta_i (i < K) of the Bose function, from the
+// two tridiagonal matrices Lambda (2K x 2K, 1/sqrt((2m+1)(2m+3)) beside the
+// diagonal) and Lambda' (2K-1 x 2K-1, 1/sqrt((2m+3)(2m+5))) of section "HEOM
+// formalism": xi_i = 2 / (i-th largest eigenvalue of Lambda), zeta_j likewise
+// from Lambda', eta_i = (K^2 + 3K/2) prod_j (zeta_j^2 - xi_i^2) / prod_{j != i}
+// (xi_j^2 - xi_i^2), the factors taken in pairs to stay in range.
+void pade_poles(int K, std::vector<double>& xi, std::vector<double>& eta) {
+    xi.assign(K, 0.0);
+    eta.assign(K, 0.0);
+    if (K < 1) return;
+    std::vector<double> e(2 * K - 1), ep(std::max(2 * K - 2, 0));
+    for (int m = 1; m <= 2 * K - 1; ++m) e[m - 1] = 1.0 / std::sqrt((2.0 * m + 1) * (2.0 * m + 3));
+    for (int m = 1; m <= 2 * K - 2; ++m) ep[m - 1] = 1.0 / std::sqrt((2.0 * m + 3) * (2.0 * m + 5));
+    const std::vector<double> ev = tridiag_eigenvalues_desc(e, 2 * K);
+    const std::vector<double> evp = tridiag_eigenvalues_desc(ep, 2 * K - 1);
+    std::vector<double> zeta(K - 1);
+    for (int i = 0; i < K; ++i) xi[i] = 2.0 / ev[i];
+    for (int j = 0; j < K - 1; ++j) zeta[j] = 2.0 / evp[j];
+    for (int i = 0; i < K; ++i) {
+        double r = K * K + 1.5 * K;
+        for (int j = 0, jd = 0; j < K - 1; ++j, ++jd) {
+            if (jd == i) ++jd;
+            r *= (zeta[j] * zeta[j] - xi[i] * xi[i]) / (xi[jd] * xi[jd] - xi[i] * xi[i]);
+        }
+        eta[i] = r;
+    }
+}
+
 // Everything derived from a problem on the host.
 struct Derived {
     int N = 0, W = 0, D = 0, B = 0, precision = 0;
@@ -147,7 +210,7 @@ heom_status derive(const heom_problem* p, Derived& d) {
     if (p->precision != HEOM_FP64 && p->precision != HEOM_FP32_MIXED &&
         p->precision != HEOM_FP32_HERM)
         return fail(HEOM_E_INVAL, "precision %d unknown", p->precision);
-    if (p->flags & ~15u) return fail(HEOM_E_INVAL, "unknown flags 0x%x", p->flags);
+    if (p->flags & ~31u) return fail(HEOM_E_INVAL, "unknown flags 0x%x", p->flags);
     if (!is_finite(p->temperature_K) || !(p->temperature_K > 0.0))
         return fail(HEOM_E_INVAL, "temperature must be finite and > 0");
     d.N = N;
@@ -183,6 +246,8 @@ heom_status derive(const heom_problem* p, Derived& d) {
         if (!is_finite(bt.tau_fs) || !(bt.tau_fs > 0.0))
             return fail(HEOM_E_INVAL, "bath %d tau must be finite and > 0", b);
         if (bt.n_matsubara < 0) return fail(HEOM_E_INVAL, "bath %d n_matsubara < 0", b);
+        if ((p->flags & HEOM_FLAG_PADE) && bt.n_matsubara > kMaxPade)
+            return fail(HEOM_E_RANGE, "bath %d: more than %d Pade poles", b, kMaxPade);
         W += 1 + bt.n_matsubara;
         if (W > 255) return fail(HEOM_E_RANGE, "more than 255 modes");
     }
@@ -192,16 +257,30 @@ heom_status derive(const heom_problem* p, Derived& d) {
         const double lam = bt.lambda_cm * kCmToRadFs;
         const double nu = 1.0 / bt.tau_fs;
         double sum_c_over_g = 0.0;
+        const bool pade = (p->flags & HEOM_FLAG_PADE) != 0;
+        std::vector<double> xi, eta;
+        if (pade) pade_poles(bt.n_matsubara, xi, eta);
         for (int k = 0; k <= bt.n_matsubara; ++k) {
             double g, c;
             if (k == 0) {
                 g = nu;
-                c = lam * nu / std::tan(0.5 * beta * nu);  // lambda nu cot(beta nu / 2)
+                if (pade) {
+                    // Pade form of lambda nu cot(beta nu / 2), sum over the poles j
+                    double s = 1.0;
+                    for (size_t j = 0; j < xi.size(); ++j) {
+                        const double a = xi[j] / beta;
+                        s -= 2.0 * eta[j] * nu * nu / (a * a - nu * nu);
+                    }
+                    c = 2.0 * lam / beta * s;
+                } else {
+                    c = lam * nu / std::tan(0.5 * beta * nu);  // lambda nu cot(beta nu / 2)
+                }
             } else {
-                g = 2.0 * M_PI * k / beta;  // Matsubara frequency
+                // Pade pole xi_k / (beta hbar), or the Matsubara frequency
+                g = pade ? xi[k - 1] / beta : 2.0 * M_PI * k / beta;
                 if (std::fabs(g - nu) <= 1e-12 * nu)
-                    return fail(HEOM_E_INVAL, "bath %d: Matsubara rate %d equals nu", b, k);
-                c = 4.0 * lam * nu / beta * g / (g * g - nu * nu);
+                    return fail(HEOM_E_INVAL, "bath %d: rate of mode %d equals nu", b, k);
+                c = 4.0 * lam * nu / beta * (pade ? eta[k - 1] : 1.0) * g / (g * g - nu * nu);
             }
             sum_c_over_g += c / g;
             d.mode_site.push_back(bt.state);
@@ -472,6 +551,26 @@ heom_status heom_copy_tables(const heom_hierarchy* h, uint8_t* tuples, int32_t* 
     if (level)
         HIP_TRY(hipMemcpyAsync(level, h->t.level, h->t.n_ado, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    return HEOM_OK;
+}
+
+static void copy_coefficients(const Derived& d, double* gamma, double* c, double* lamnu,
+                              double* delta_state) {
+    for (int l = 0; l < d.W; ++l) {
+        if (gamma) gamma[l] = d.mode_gamma[l];
+        if (c) c[l] = d.mode_c_raw[l];
+        if (lamnu) lamnu[l] = (d.flags & HEOM_FLAG_STANDARD_GAUGE) ? -d.mode_lamnu[l] : d.mode_lamnu[l];
+    }
+    if (delta_state)
+        for (int s = 0; s < d.N; ++s) delta_state[s] = d.delta_state[s];
+}
+
+heom_status heom_problem_coefficients(const heom_problem* problem, double* gamma, double* c,
+                                      double* lamnu, double* delta_state) {
+    Derived d;
+    heom_status s = derive(problem, d);
+    if (s != HEOM_OK) return s;
+    copy_coefficients(d, gamma, c, lamnu, delta_state);
     return HEOM_OK;
 }
 

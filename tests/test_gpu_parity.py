@@ -50,13 +50,15 @@ def test_tables_bit_exact(heom, orc, W, D):
 
 
 def test_coefficients_match_oracle(heom, orc):
-    for prob in (hi.dimer(), hi.fmo_like(), hi.aggregate24(), hi.random_problem(1, 4, M=3, D=1)):
+    for prob in (hi.dimer(), hi.fmo_like(), hi.aggregate24(), hi.random_problem(1, 4, M=3, D=1),
+                 hi.fmo_like_pade(30.0, 3, 3)):
         h = heom.Hierarchy(prob)
         g, c, ln, ds = h.coefficients()
         off = 0
+        pade = bool(prob.get("flags", 0) & hi.FLAG_PADE)
         for b in prob["baths"]:
             rg, rc, rln, rd = orc.bath_coefficients(b["lambda_cm"], b["tau_fs"],
-                                                    prob["temperature_K"], b["matsubara"])
+                                                    prob["temperature_K"], b["matsubara"], pade)
             K = b["matsubara"] + 1
             assert np.allclose(g[off:off + K], rg, rtol=1e-15, atol=0)
             assert np.allclose(c[off:off + K], rc, rtol=1e-14, atol=0)
@@ -98,6 +100,10 @@ RHS_CASES = [
     (24, 20, 3, 1, 5, {}),
     (25, 40, 3, 1, 5, {}),
     (26, 14, 14, 1, 3, {}),     # the serving mix's largest N on the FMA path
+    # Pade modes (only the coefficients differ): FMA and matrix-core paths
+    (27, 5, 5, 2, 2, {"flags": 16}),
+    (28, 7, 7, 3, 3, {"flags": 16}),
+    (29, 24, 24, 1, 2, {"flags": 16}),
 ]
 FP32_CASES = RHS_CASES[:14] + RHS_CASES[20:]
 

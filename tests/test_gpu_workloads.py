@@ -77,6 +77,22 @@ def test_fmo_like_absorption_spectrum(heom, orc):
         assert rel <= (1e-12 if precision == 0 else 1e-4), rel
 
 
+# ------------------------------------ low temperature, Pade expansion ----
+
+@pytest.mark.parametrize("T,poles,steps,dt", [(77.0, 1, 200, 1.0), (30.0, 3, 100, 0.5)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
+def test_fmo_like_pade_low_temperature(heom, orc, T, poles, steps, dt, precision, tol):
+    # the paper's working settings (D, K) = (3, 2) at 77 K and (3, 4) at 30 K
+    _case("fmo_like pade", T, poles, precision)
+    prob = hi.fmo_like_pade(T, 3, poles, n_steps=steps, dt_fs=dt)
+    _, rec_ref = orc.run(prob)
+    h = heom.Hierarchy(prob, precision)
+    st = h.new_state(prob["rho0"])
+    rec = h.propagate(st, dt, steps, 1, prob["observable"], hermitian=True)
+    assert np.max(np.abs(rec[:, :7] - rec_ref[:, :7])) <= tol
+    assert np.max(np.abs(rec[:, 7] - 1.0)) <= 1e-12
+
+
 # ----------------------------------------------- aggregates, full size ----
 
 def _level_ranges(W, D, width):

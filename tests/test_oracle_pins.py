@@ -163,6 +163,113 @@ def test_first_matsubara_frequency(orc):
     assert g[0] == pytest.approx(1.0 / 50.0, rel=1e-15)
 
 
+# ---------------------------------------------------------- Pade modes ----
+
+def _bose_pade(x, K, orc):
+    xi, eta = orc.pade_poles(K)
+    return 1.0 / x + 0.5 + sum(2.0 * e * x / (x * x + z * z) for z, e in zip(xi, eta))
+
+
+def test_pade_k1_closed_form(orc):
+    # Lambda is [[0, 1/sqrt(15)], [1/sqrt(15), 0]] and Lambda' = [0]: xi = 2 sqrt(15),
+    # eta = K^2 + 3K/2 = 5/2.  1/x + 1/2 + 5x/(x^2 + 60) then matches the Taylor
+    # series of 1/(1 - e^-x) = 1/x + 1/2 + x/12 - x^3/720 + ... through x^3.
+    xi, eta = orc.pade_poles(1)
+    assert xi[0] == pytest.approx(2.0 * np.sqrt(15.0), rel=1e-14)
+    assert eta[0] == pytest.approx(2.5, rel=1e-14)
+    x = 1e-2
+    err = _bose_pade(np.array([x]), 1, orc)[0] - 1.0 / (-np.expm1(-x))
+    assert abs(err) < 1e-11   # the next term is O(x^5)
+
+
+def test_pade_poles_match_eigvalsh(orc):
+    # an independent eigensolver on the same two matrices
+    for K in (2, 3, 5, 8, 16):
+        def lam(n, shift):
+            m = np.arange(1, n)
+            off = 1.0 / np.sqrt((2.0 * m + shift) * (2.0 * m + shift + 2.0))
+            return np.diag(off, 1) + np.diag(off, -1)
+        ev = np.sort(np.linalg.eigvalsh(lam(2 * K, 1)))[::-1][:K]
+        evp = np.sort(np.linalg.eigvalsh(lam(2 * K - 1, 3)))[::-1][:K - 1]
+        xi, eta = orc.pade_poles(K)
+        assert np.allclose(xi, 2.0 / ev, rtol=1e-12, atol=0)
+        zeta = 2.0 / evp
+        ref = np.array([(K * K + 1.5 * K) * np.prod(zeta**2 - x**2) /
+                        np.prod([xi[j]**2 - x**2 for j in range(K) if j != i])
+                        for i, x in enumerate(xi)])
+        assert np.allclose(eta, ref, rtol=1e-10, atol=0)
+
+
+def test_pade_reproduces_bose_function(orc):
+    # the [K-1/K] approximant converges fast on |x| < 2 pi (Hu, Xu and Yan)
+    x = np.linspace(-6.0, 6.0, 241)
+    x = x[np.abs(x) > 1e-9]
+    exact = 1.0 / (-np.expm1(-x))
+    errs = [np.max(np.abs(_bose_pade(x, K, orc) - exact)) for K in (1, 2, 3, 4, 6)]
+    assert errs[0] < 3e-2 and errs[1] < 3e-4 and errs[2] < 1e-6 and errs[3] < 1e-9
+    assert errs[4] < 1e-13
+    assert all(a > b for a, b in zip(errs[:4], errs[1:4]))
+
+
+def test_pade_first_poles_tend_to_matsubara(orc):
+    # the lowest poles become the Matsubara frequencies 2 pi j with unit weight
+    xi, eta = orc.pade_poles(20)
+    assert np.allclose(xi[:5], 2 * np.pi * np.arange(1, 6), rtol=1e-12)
+    assert np.allclose(eta[:5], 1.0, rtol=1e-12)
+    assert np.all(eta > 0) and np.all(np.diff(xi) > 0)
+
+
+@pytest.mark.parametrize("T", [300.0, 77.0, 30.0])
+def test_pade_sum_rule_and_cot(orc, T):
+    # with c(b,0) in its Pade form, sum_k c_k / gamma_k = 2 lambda / (beta nu)
+    # for every K, so the correction coefficient vanishes; c(b,0) tends to
+    # lambda nu cot(beta nu / 2)
+    lam, tau = 35.0, 50.0
+    beta = 1.0 / (0.6950348004 * T * TWO_PI_C)
+    l, nu = lam * TWO_PI_C, 1.0 / tau
+    for K in (0, 1, 2, 4, 8):
+        g, c, lamnu, d = orc.bath_coefficients(lam, tau, T, K, pade=True)
+        assert abs(d) <= 1e-13 * (2 * l / (beta * nu))
+        assert g[0] == nu and lamnu == pytest.approx(l * nu, rel=1e-15)
+    g, c, _, _ = orc.bath_coefficients(lam, tau, T, 12, pade=True)
+    assert c[0] == pytest.approx(l * nu / np.tan(beta * nu / 2), rel=1e-11)
+
+
+@pytest.mark.parametrize("lam,tau,T", [(35.0, 50.0, 300.0), (20.0, 30.0, 77.0),
+                                       (50.0, 100.0, 30.0)])
+def test_pade_correlation_matches_spectral_density(orc, lam, tau, T):
+    g, c, lamnu, _ = orc.bath_coefficients(lam, tau, T, 40, pade=True)
+    for t in (5.0, 20.0, 60.0):
+        re_q, _ = _corr_quadrature(lam, tau, T, t)
+        assert abs(np.sum(c * np.exp(-g * t)) - re_q) <= 5e-6 * max(abs(re_q), abs(c[0]))
+    # at 30 K four poles already beat four Matsubara terms at short times
+    if T == 30.0:
+        re_q, _ = _corr_quadrature(lam, tau, T, 5.0)
+        gp, cp, _, _ = orc.bath_coefficients(lam, tau, T, 4, pade=True)
+        gm, cm, _, _ = orc.bath_coefficients(lam, tau, T, 4)
+        assert abs(np.sum(cp * np.exp(-gp * 5.0)) - re_q) < abs(np.sum(cm * np.exp(-gm * 5.0)) - re_q)
+
+
+def test_pade_pure_dephasing_cumulant(orc):
+    # the exactly solvable dephasing limit (see the Matsubara test below) with
+    # Pade modes: the hierarchy reproduces the cumulant of its own expansion
+    eps, lam, tau, T, K = 100.0, 20.0, 50.0, 77.0, 2
+    prob = {"H": np.diag([0.0, eps]), "temperature_K": T, "depth": 10, "flags": hi.FLAG_PADE,
+            "baths": [{"state": 1, "lambda_cm": lam, "tau_fs": tau, "matsubara": K}]}
+    W, n = orc.sizes(prob)
+    g, c, lamnu, delta = orc.bath_coefficients(lam, tau, T, K, pade=True)
+    ct = c.astype(complex)
+    ct[0] -= 1j * lamnu
+    s = orc.initial_state(prob, n, np.full((2, 2), 0.5, complex))
+    t = 0.0
+    for _ in range(4):
+        s, _ = orc.propagate(prob, s, 0.25, 200, 200)
+        t += 50.0
+        gt = np.sum(ct / g**2 * (g * t - 1 + np.exp(-g * t))) + delta * t
+        ref = 0.5 * np.exp(-1j * eps * TWO_PI_C * t - gt)
+        assert abs(s[0][1, 0] - ref) < 1e-8
+
+
 # ------------------------------------------------------------------- RHS ----
 
 def _small_problems():
