@@ -540,7 +540,10 @@ __global__ __launch_bounds__(fma_block(sizeof(T))) __attribute__((amdgpu_waves_p
             return;
         }
     }
-    const int b = xcd_remap(blockIdx.x - s0_blocks, gridDim.x - s0_blocks);
+    const int n_first = BATCHED ? 0
+                                : min((single.n_low + single.ados_per_tile - 1) / single.ados_per_tile,
+                                      (int)gridDim.x - s0_blocks);
+    const int b = xcd_remap_low(blockIdx.x - s0_blocks, gridDim.x - s0_blocks, n_first);
     const Job& J = JobOf<BATCHED>::get(single, jobs, n_jobs, b);
     const Tables& t = J.t;
     const int N = t.N, NN = N * N, W = t.W, D = t.D, Dm = D > 0 ? D : 1;
