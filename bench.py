@@ -38,6 +38,10 @@ WORKLOADS = {
     # the largest request of the serving mix as a single propagation
     # (14 sites, W = 28, depth 5: 237336 ADOs of 14x14, FMA kernel)
     "mix_largest": lambda: _mix_largest(),
+    # the paper's FMO reference setting (D, K) = (6, 6) with the Pade
+    # expansion at 300 K: 7 sites, 5 poles per bath, 12271512 ADOs of 7x7;
+    # dt = 0.1 fs (the step-size guard's limit for these rates is 0.14 fs)
+    "fmo66_pade": lambda: hi.fmo_like_pade(300.0, 6, 5, n_steps=20, dt_fs=0.1),
 }
 
 
@@ -292,7 +296,8 @@ def main():
     prob = WORKLOADS[args.workload]()
     precision = {"fp32_mixed": heom.FP32_MIXED, "fp32_herm": heom.FP32_HERM,
                  "fp64": heom.FP64}[args.precision]
-    steps = args.steps if args.steps is not None else (50 if args.workload == "aggregate48" else 200)
+    steps = args.steps if args.steps is not None else {"aggregate48": 50, "fmo66_pade": 20}.get(
+        args.workload, 200)
     warmup = args.warmup if args.warmup is not None else 5
     torch.cuda.set_device(0)
     h = heom.Hierarchy(prob, precision)
