@@ -90,7 +90,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="aggregate48",
-                    choices=sorted(WORKLOADS) + ["serve", "copy"])
+                    choices=sorted(WORKLOADS) + ["serve", "copy", "fluorescence"])
     ap.add_argument("--copy-gib", type=float, default=4.0,
                     help="--workload copy: bytes read (and written) per copy")
     ap.add_argument("--precision", default="fp32_mixed", choices=["fp32_mixed", "fp32_herm", "fp64"])
@@ -248,6 +248,46 @@ def run_serve(args):
     print(json.dumps(line), flush=True)
 
 
+def run_fluorescence(args):
+    """Static fluorescence of the FMO-like system (section "Static
+    Fluorescence Spectra"): thermal state by a 2 ps population run from the
+    Boltzmann state, then sigma_u(inf) mu_p^+ propagated for 1 ps in each of
+    three directions, and the spectrum.  Times the whole computation."""
+    import torch
+    import paper_1803_03498_amd as heom
+    torch.cuda.set_device(0)
+    precision = heom.FP64 if args.precision == "fp64" else heom.FP32_MIXED
+    base = hi.fmo_like()
+    dip = hi.unit_vectors(np.random.default_rng(70), 7)
+    relax, emis = hi.fluorescence_runs(base["H"], dip, base["baths"], 300.0, base["depth"], 1.0,
+                                       2000, 1000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    he = heom.Hierarchy(relax, precision)
+    st = he.new_state(relax["rho0"])
+    he.propagate(st, 1.0, relax["n_steps"], relax["record_every"], hermitian=True)
+    P = []
+    for r in emis:
+        hf = heom.Hierarchy(r, precision)
+        y = hf.new_state()
+        heom.emission_start(he, st, hf, y, r["observable"]["mu"][1:])
+        rec = hf.propagate(y, 1.0, r["n_steps"], 1, r["observable"], hermitian=False)
+        P.append(rec[:, 0] + 1j * rec[:, 1])
+        print("fluorescence: direction %d done, %.2f s" % (len(P), time.perf_counter() - t0),
+              file=sys.stderr, flush=True)
+    S = heom.spectrum(np.stack(P), 1.0, np.arange(-1000.0, 1001.0, 1.0))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    n = he.n_ado
+    updates = n * (relax["n_steps"] + 3 * emis[0]["n_steps"])
+    print(json.dumps({"workload": "fluorescence: fmo_like thermal state (2000 steps) + 3 x 1000 "
+                                  "emission steps, 3060 ADOs, spectrum on 2001 points",
+                      "precision": args.precision, "seconds": el,
+                      "ado_updates_per_s": updates / el,
+                      "peak_cm_rel": float(np.arange(-1000.0, 1001.0, 1.0)[np.argmax(S)])}),
+          flush=True)
+
+
 def run_copy(args):
     """A plain device-to-device copy of known size: the reference against
     which the HBM byte counters of a profiler run are scaled."""
@@ -276,6 +316,9 @@ def main():
     args = parse()
     if args.workload == "copy":
         run_copy(args)
+        return
+    if args.workload == "fluorescence":
+        run_fluorescence(args)
         return
     if args.workload == "serve":
         if args.gpus != 1:

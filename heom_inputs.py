@@ -134,6 +134,34 @@ def absorption_runs(H_sites, dip, baths_sites, T, depth, dt, n_steps, record_eve
     return runs
 
 
+def boltzmann_rho(H_sites, T):
+    """exp(-H/(k_B T)) / Tr (eq. rho_Boltzmann), H in cm^-1 (input preparation)."""
+    kT = 0.6950348004 * T
+    w, v = np.linalg.eigh(H_sites)
+    p = np.exp(-(w - w.min()) / kT)
+    p /= p.sum()
+    return (v * p) @ v.T
+
+
+def fluorescence_runs(H_sites, dip, baths_sites, T, depth, dt, n_relax, n_steps, record_every=1):
+    """Static fluorescence (section "Static Fluorescence Spectra"): a
+    population run of the excited states from the Boltzmann state for
+    n_relax steps (the long-time propagation route to the thermal state
+    sigma_u(inf)), then three dipole-correlation runs (x, y, z) of the
+    (N+1)-state system started from sigma_u(inf) mu_p^+ (all ADOs) in the
+    frame rotating at the mean site energy."""
+    n = H_sites.shape[0]
+    wref = float(np.mean(np.diag(H_sites)))
+    relax = {"H": H_sites - wref * np.eye(n), "baths": [dict(b) for b in baths_sites],
+             "temperature_K": T, "depth": depth, "flags": 0, "dt_fs": dt, "n_steps": n_relax,
+             "record_every": n_relax if n_relax > 0 else 1, "rho0": boltzmann_rho(H_sites, T),
+             "observable": {"kind": "population"}}
+    emis = absorption_runs(H_sites, dip, baths_sites, T, depth, dt, n_steps, record_every)
+    for r in emis:
+        r["rho0"] = None  # the start is sigma_u(inf) mu_p^+, built from the relaxed state
+    return relax, emis
+
+
 # --------------------------------------------------------------------------
 # Named workloads
 # --------------------------------------------------------------------------

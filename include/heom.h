@@ -228,6 +228,25 @@ heom_status heom_get_state(const heom_hierarchy* h, heom_state s, void* host_sig
 heom_status heom_set_state(const heom_hierarchy* h, heom_state s, const void* host_sigma0,
                            const void* host_rest, void* stream);
 
+/* Start of a static fluorescence run (section "Static Fluorescence
+ * Spectra"): the dipole operator acts on every ADO of the thermalised
+ * hierarchy.  `exc` describes the N excited states alone (its state
+ * `exc_state` holds sigma_u(inf), e.g. after a long population run from the
+ * Boltzmann state); `full` the same baths on N + 1 states with the ground
+ * state at index 0 and site a at index 1 + a (equal mode count and depth, so
+ * equal ADO numbering).  Writes into `full_state`, for every ADO u,
+ *   Y_u[1 + a][0] = sum_b sigma_u(inf)[a][b] mu[b],   all other elements 0,
+ * i.e. sigma_u(inf) mu^+ restricted to the (e, g) block.  Propagating Y with
+ * the dipole observable (mu on indices 1..N, ground 0, hermitian = 0) gives
+ * the emission correlation whose heom_spectrum is the fluorescence of
+ * direction mu.  mu: host pointer, N doubles (e_p . d_a).  Both hierarchies
+ * on the current device; exc in HEOM_FP64 or HEOM_FP32_MIXED, full in
+ * either (elements converted).  Enqueued on `stream` (not synchronised).
+ * HEOM_E_INVAL on a mismatch (N, W, D) or a packed precision. */
+heom_status heom_emission_start(const heom_hierarchy* exc, heom_state exc_state,
+                                const heom_hierarchy* full, heom_state full_state,
+                                const double* mu, void* stream);
+
 /* Host only: linear absorption spectrum from dipole-correlation records
  * (eq. lin_abs_mukamel on a finite window, section "Linear absorption
  * spectra"):  S(w_k) = Re sum_p sum_n c_n exp(i w_k t_n) P_p(t_n) dt,

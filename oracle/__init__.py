@@ -197,6 +197,33 @@ def initial_state(prob, n_ado, rho0):
     return s
 
 
+def emission_start(state, mu):
+    """Start of a fluorescence run (section "Static Fluorescence Spectra": the
+    dipole operator acts on every ADO): for the thermalised excited-state
+    hierarchy `state` [n][N][N], the (N+1)-state ADOs Y_u = sigma_u mu^+,
+    i.e. Y_u[1 + a][0] = sum_b sigma_u[a][b] mu[b], ground state at index 0."""
+    state = np.asarray(state, np.complex128)
+    n, N, _ = state.shape
+    Y = np.zeros((n, N + 1, N + 1), np.complex128)
+    Y[:, 1:, 0] = state @ np.asarray(mu, np.float64)
+    return Y
+
+
+def fluorescence(relax, emis):
+    """Oracle fluorescence pipeline: relax the excited-state hierarchy from
+    its Boltzmann start, then propagate sigma_u(inf) mu_p^+ for each
+    direction.  Returns (thermal state, P [n_dir][n_t] complex)."""
+    W, n = sizes(relax)
+    s0 = initial_state(relax, n, relax["rho0"])
+    st, _ = propagate(relax, s0, relax["dt_fs"], relax["n_steps"], relax["record_every"])
+    P = []
+    for r in emis:
+        Y = emission_start(st, r["observable"]["mu"][1:])
+        _, rec = propagate(r, Y, r["dt_fs"], r["n_steps"], r["record_every"], r["observable"])
+        P.append(rec[:, 0] + 1j * rec[:, 1])
+    return st, np.stack(P)
+
+
 def run(run_spec, n_steps=None):
     """Propagate a run dict (see heom_inputs); returns (final state, records)."""
     W, n = sizes(run_spec)

@@ -17,7 +17,7 @@ import numpy as np
 from . import _abi
 from ._abi import FP32_HERM, FP32_MIXED, FP64, OBS_DIPOLE, OBS_POPULATION, HeomError, check, load
 
-__all__ = ["FP64", "FP32_MIXED", "FP32_HERM", "problem_coefficients", "pack_hermitian", "unpack_hermitian", "OBS_POPULATION", "OBS_DIPOLE", "HeomError", "Problem", "plan",
+__all__ = ["FP64", "FP32_MIXED", "FP32_HERM", "problem_coefficients", "emission_start", "pack_hermitian", "unpack_hermitian", "OBS_POPULATION", "OBS_DIPOLE", "HeomError", "Problem", "plan",
            "Hierarchy", "Server", "spectrum", "load"]
 
 
@@ -249,6 +249,17 @@ class Hierarchy:
         hr = np.ascontiguousarray(host_rest, dtype=self._host_rest_dtype)
         check(load().heom_set_state(self.handle, self._st(state), h0.ctypes.data,
                                     hr.ctypes.data if hr.size else None, _stream_handle()))
+
+
+def emission_start(h_exc, state_exc, h_full, state_full, mu, stream=None):
+    """heom_emission_start: Y_u = sigma_u(inf) mu^+ of every ADO of the
+    thermalised N-state hierarchy, embedded into the (N+1)-state state_full."""
+    m = np.ascontiguousarray(mu, dtype=np.float64)
+    if m.shape != (h_exc.N,):
+        raise ValueError("mu must have N entries")
+    check(load().heom_emission_start(h_exc.handle, Hierarchy._st(state_exc), h_full.handle,
+                                     Hierarchy._st(state_full), m.ctypes.data,
+                                     _stream_handle(stream)))
 
 
 class Server:

@@ -858,6 +858,28 @@ heom_status heom_timing_read(double* bulk_ms, int64_t* bulk_launches, double* bu
     return HEOM_OK;
 }
 
+heom_status heom_emission_start(const heom_hierarchy* exc, heom_state exc_state,
+                                const heom_hierarchy* full, heom_state full_state,
+                                const double* mu, void* stream) {
+    if (!exc || !full || !mu) return fail(HEOM_E_INVAL, "NULL hierarchy or mu");
+    heom_status rc;
+    if ((rc = check_state(exc, exc_state, "exc_state")) != HEOM_OK) return rc;
+    if ((rc = check_state(full, full_state, "full_state")) != HEOM_OK) return rc;
+    if (full->t.N != exc->t.N + 1 || full->t.W != exc->t.W || full->t.D != exc->t.D ||
+        full->t.n_ado != exc->t.n_ado)
+        return fail(HEOM_E_INVAL, "full must have N + 1 states and the same modes and depth as exc");
+    if (exc->d.precision == HEOM_FP32_HERM || full->d.precision == HEOM_FP32_HERM)
+        return fail(HEOM_E_INVAL, "emission start takes complex storage (FP64 or FP32-mixed)");
+    for (int b = 0; b < exc->t.N; ++b)
+        if (!is_finite(mu[b])) return fail(HEOM_E_INVAL, "mu[%d] is not finite", b);
+    hipError_t e = heom::launch_emission_start(
+        exc_state.sigma0, exc_state.rest, exc->d.precision == HEOM_FP64 ? 0 : 1, full_state.sigma0,
+        full_state.rest, full->d.precision == HEOM_FP64 ? 0 : 1, mu, exc->t.N, exc->t.n_ado,
+        static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(HEOM_E_DEVICE, "emission start launch: %s", hipGetErrorString(e));
+    return HEOM_OK;
+}
+
 heom_status heom_get_state(const heom_hierarchy* h, heom_state s, void* host_sigma0,
                            void* host_rest, void* stream) {
     if (!h) return fail(HEOM_E_INVAL, "hierarchy is NULL");

@@ -95,6 +95,11 @@ struct StageSpec {
 hipError_t launch_enumerate(const Tables& t, hipStream_t stream);
 // Complex64 copy of the packed ADOs 1..n into `mirror` (Hermitian-packed storage).
 hipError_t launch_pk_mirror(const void* packed_rest, void* mirror, int N, int n, hipStream_t stream);
+// Fluorescence start: Y_u = sigma_u mu^+ embedded in the (N+1)-state ADOs
+// (precisions 0 = complex128, 1 = complex64 for the bulk of each side).
+hipError_t launch_emission_start(const void* in_sig0, const void* in_rest, int in_prec,
+                                 void* out_sig0, void* out_rest, int out_prec, const double* mu,
+                                 int N, int64_t n_ado, hipStream_t stream);
 // ev_begin/ev_end (may be null) bracket the bulk-kernel launch.
 hipError_t launch_stage(const Job& single, const Job* jobs_dev, int n_jobs, int total_tiles,
                         int precision, const StageSpec& sp, hipStream_t stream,

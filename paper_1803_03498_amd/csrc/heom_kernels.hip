@@ -1566,6 +1566,66 @@ hipError_t launch_pk_mirror(const void* packed_rest, void* mirror, int N, int n,
     return hipGetLastError();
 }
 
+// Fluorescence start (section "Static Fluorescence Spectra": the dipole
+// operator acts on all ADOs): element (i, j) of the (N+1)-state ADO u is
+// sum_b sigma_u[i-1][b] mu[b] for j = 0 < i, zero elsewhere.  One thread per
+// output element; ADO 0 is complex128 on both sides.
+struct MuArg {
+    double mu[64];
+};
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_emission_start(const void* in_sig0, const void* in_rest,
+                                                        void* out_sig0, void* out_rest, MuArg mu,
+                                                        int N, int64_t total) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    const int M = N + 1, MM = M * M;
+    const int64_t u = idx / MM;
+    const int e = (int)(idx - u * MM), i = e / M, j = e - (e / M) * M;
+    double yr = 0.0, yi = 0.0;
+    if (j == 0 && i > 0) {
+        for (int b = 0; b < N; ++b) {
+            const size_t at = (size_t)(i - 1) * N + b;
+            double xr, xi;
+            if (u == 0) {
+                const cpx<double> x = ld<double>(in_sig0, at);
+                xr = x.re;
+                xi = x.im;
+            } else {
+                const cpx<TI> x = ld<TI>(in_rest, (size_t)(u - 1) * N * N + at);
+                xr = (double)x.re;
+                xi = (double)x.im;
+            }
+            yr += xr * mu.mu[b];
+            yi += xi * mu.mu[b];
+        }
+    }
+    if (u == 0)
+        st<double>(out_sig0, (size_t)e, cpx<double>{yr, yi});
+    else
+        st<TO>(out_rest, (size_t)(u - 1) * MM + e, cpx<TO>{(TO)yr, (TO)yi});
+}
+
+hipError_t launch_emission_start(const void* in_sig0, const void* in_rest, int in_prec,
+                                 void* out_sig0, void* out_rest, int out_prec, const double* mu,
+                                 int N, int64_t n_ado, hipStream_t stream) {
+    if (N < 1 || N > 63 || n_ado < 1) return hipErrorInvalidValue;
+    MuArg m{};
+    for (int b = 0; b < N; ++b) m.mu[b] = mu[b];
+    const int64_t total = n_ado * (int64_t)(N + 1) * (N + 1);
+    const dim3 grid((unsigned)((total + 255) / 256)), block(256);
+    if (in_prec == 0 && out_prec == 0)
+        hipLaunchKernelGGL((k_emission_start<double, double>), grid, block, 0, stream, in_sig0, in_rest, out_sig0, out_rest, m, N, total);
+    else if (in_prec == 0)
+        hipLaunchKernelGGL((k_emission_start<double, float>), grid, block, 0, stream, in_sig0, in_rest, out_sig0, out_rest, m, N, total);
+    else if (out_prec == 0)
+        hipLaunchKernelGGL((k_emission_start<float, double>), grid, block, 0, stream, in_sig0, in_rest, out_sig0, out_rest, m, N, total);
+    else
+        hipLaunchKernelGGL((k_emission_start<float, float>), grid, block, 0, stream, in_sig0, in_rest, out_sig0, out_rest, m, N, total);
+    return hipGetLastError();
+}
+
 hipError_t launch_enumerate(const Tables& t, hipStream_t stream) {
     if (t.n_ado <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_enumerate, dim3((t.n_ado + 255) / 256), dim3(256), 0, stream, t);

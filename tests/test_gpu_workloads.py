@@ -93,6 +93,56 @@ def test_fmo_like_pade_low_temperature(heom, orc, T, poles, steps, dt, precision
     assert np.max(np.abs(rec[:, 7] - 1.0)) <= 1e-12
 
 
+# ------------------------------------------------ static fluorescence ----
+
+def _gpu_fluorescence(heom, relax, emis, prec_exc, prec_full):
+    he = heom.Hierarchy(relax, prec_exc)
+    st = he.new_state(relax["rho0"])
+    he.propagate(st, relax["dt_fs"], relax["n_steps"], relax["record_every"], hermitian=True)
+    P = []
+    for r in emis:
+        hf = heom.Hierarchy(r, prec_full)
+        y = hf.new_state()
+        heom.emission_start(he, st, hf, y, r["observable"]["mu"][1:])
+        rec = hf.propagate(y, r["dt_fs"], r["n_steps"], r["record_every"], r["observable"],
+                           hermitian=False)
+        P.append(rec[:, 0] + 1j * rec[:, 1])
+    return he.state_to_numpy(st), np.stack(P)
+
+
+@pytest.mark.parametrize("N,M,D", [(2, 0, 4), (3, 1, 3), (7, 1, 3)])
+@pytest.mark.parametrize("precs,tol", [((0, 0), 1e-12), ((1, 1), 1e-5), ((0, 1), 1e-5)])
+def test_fluorescence_pipeline(heom, orc, N, M, D, precs, tol):
+    _case("fluorescence", N, M, D, precs)
+    rng = np.random.default_rng(40 + N)
+    H = hi.fmo_like_hamiltonian(rng, N)
+    dip = hi.unit_vectors(rng, N)
+    baths = [{"state": s, "lambda_cm": 35.0, "tau_fs": 50.0, "matsubara": M} for s in range(N)]
+    relax, emis = hi.fluorescence_runs(H, dip, baths, 300.0, D, 1.0, 300, 200)
+    st_ref, P_ref = orc.fluorescence(relax, emis)
+    st, P = _gpu_fluorescence(heom, relax, emis, *precs)
+    scale = np.max(np.abs(P_ref))
+    assert np.max(np.abs(P - P_ref)) <= tol * scale
+    if precs == (0, 0):
+        assert np.max(np.abs(st - st_ref)) <= 1e-12
+
+
+def test_emission_start_rejects_mismatch(heom):
+    from paper_1803_03498_amd._abi import HeomError
+    rng = np.random.default_rng(1)
+    H = hi.fmo_like_hamiltonian(rng, 3)
+    baths = [{"state": s, "lambda_cm": 35.0, "tau_fs": 50.0, "matsubara": 0} for s in range(3)]
+    relax, emis = hi.fluorescence_runs(H, hi.unit_vectors(rng, 3), baths, 300.0, 2, 1.0, 1, 1)
+    he = heom.Hierarchy(relax)
+    st = he.new_state(relax["rho0"])
+    bad = dict(emis[0], depth=3)
+    hf = heom.Hierarchy(bad)
+    with pytest.raises(HeomError):
+        heom.emission_start(he, st, hf, hf.new_state(), np.ones(3))
+    with pytest.raises(HeomError):
+        heom.emission_start(he, st, he, he.new_state(), np.ones(3))
+
+
 # ----------------------------------------------- aggregates, full size ----
 
 def _level_ranges(W, D, width):

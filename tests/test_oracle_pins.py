@@ -452,6 +452,60 @@ def test_spectrum_trapezoid_closed_form(orc):
     assert np.max(np.abs(S - ref)) < 1e-9 * np.max(np.abs(ref))
 
 
+def _fluor_spectra(orc, lam, tau, D, sigma0_only=False):
+    H = np.array([[12000.0]])
+    dip = np.array([[1.0, 0.0, 0.0]])
+    baths = [{"state": 0, "lambda_cm": lam, "tau_fs": tau, "matsubara": 0}]
+    relax, emis = hi.fluorescence_runs(H, dip, baths, 300.0, D, 1.0, 5000, 3000)
+    st, P = orc.fluorescence(relax, emis[:1])
+    if sigma0_only:
+        st[1:] = 0.0
+        Y = orc.emission_start(st, emis[0]["observable"]["mu"][1:])
+        _, rec = orc.propagate(emis[0], Y, 1.0, 3000, 1, emis[0]["observable"])
+        P = (rec[:, 0] + 1j * rec[:, 1])[None]
+    _, rec = orc.run(hi.absorption_runs(H, dip, baths, 300.0, D, 1.0, 3000)[0])
+    w = np.arange(-800.0, 800.0, 1.0)
+    Sf = orc.spectrum(P, 1.0, w)
+    Sa = orc.spectrum((rec[:, 0] + 1j * rec[:, 1])[None], 1.0, w)
+    mean = lambda S: np.sum(w * S) / np.sum(S)
+    return mean(Sa), mean(Sf)
+
+
+@pytest.mark.parametrize("lam", [20.0, 35.0])
+def test_fluorescence_stokes_shift_monomer(orc, lam):
+    # One excited state with a slow Drude-Lorentz bath: the first moments of
+    # absorption and emission differ by the Stokes shift 2 lambda.  Applying
+    # the dipole to sigma_0 alone (dropping the thermal ADOs) loses it.
+    ma, mf = _fluor_spectra(orc, lam, 500.0, 16)
+    assert abs((ma - mf) - 2 * lam) <= 0.02 * 2 * lam
+    ma0, mf0 = _fluor_spectra(orc, lam, 500.0, 16, sigma0_only=True)
+    assert abs(ma0 - mf0) <= 0.05 * 2 * lam
+
+
+def test_fluorescence_lambda_zero_closed_form(orc):
+    # lambda = 0: the Boltzmann state is stationary and the emission
+    # correlation is sum_k p_k (phi_k . mu)^2 R(z_k)^n, the thermal weights
+    # of the excitons times their RK4-amplified phases.
+    rng = np.random.default_rng(3)
+    H = hi.fmo_like_hamiltonian(rng, 3)
+    dip = hi.unit_vectors(rng, 3)
+    baths = [{"state": s, "lambda_cm": 0.0, "tau_fs": 50.0, "matsubara": 0} for s in range(3)]
+    relax, emis = hi.fluorescence_runs(H, dip, baths, 300.0, 1, 1.0, 50, 200)
+    st, P = orc.fluorescence(relax, emis)
+    assert np.max(np.abs(st[0] - hi.boltzmann_rho(H, 300.0))) < 1e-13
+    wref = np.mean(np.diag(H))
+    e, v = np.linalg.eigh(H)
+    p = np.exp(-(e - e.min()) / (0.6950348004 * 300.0))
+    p /= p.sum()
+    z = -1j * (e - wref) * TWO_PI_C * 1.0
+    R = 1 + z + z**2 / 2 + z**3 / 6 + z**4 / 24
+    n = np.arange(P.shape[1])
+    for k, r in enumerate(emis):
+        amp = p * (v.T @ r["observable"]["mu"][1:]) ** 2
+        ref = (amp[None, :] * R[None, :] ** n[:, None]).sum(axis=1)
+        assert np.max(np.abs(P[k] - ref)) < 1e-12
+
+
 def test_dipole_correlation_lambda_zero(orc):
     # lambda = 0: P_p(t) = sum_e |e_p . D_e|^2 exp(-i eps_e t) over excitons.
     runs = hi.fmo_like_absorption(n_steps=200)
