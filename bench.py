@@ -90,7 +90,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="aggregate48",
-                    choices=sorted(WORKLOADS) + ["serve", "copy", "fluorescence"])
+                    choices=sorted(WORKLOADS) + ["serve", "copy", "fluorescence", "absorption"])
     ap.add_argument("--copy-gib", type=float, default=4.0,
                     help="--workload copy: bytes read (and written) per copy")
     ap.add_argument("--precision", default="fp32_mixed", choices=["fp32_mixed", "fp32_herm", "fp64"])
@@ -288,6 +288,39 @@ def run_fluorescence(args):
           flush=True)
 
 
+def run_absorption(args):
+    """Linear absorption of the FMO-like system (3 directions, 1000 steps,
+    FP64): three full (N+1)-state dipole-correlation runs against one
+    coherence-block run of the three directions.  Times both."""
+    import torch
+    import paper_1803_03498_amd as heom
+    torch.cuda.set_device(0)
+    runs = hi.fmo_like_absorption()
+    out = {"workload": "absorption: fmo_like, 3 directions x 1000 RK4 steps, 3060 ADOs, FP64"}
+    for form in ("full", "block"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if form == "full":
+            for r in runs:
+                h = heom.Hierarchy(r, heom.FP64)
+                st = h.new_state(r["rho0"])
+                h.propagate(st, r["dt_fs"], r["n_steps"], 1, r["observable"], hermitian=False)
+        else:
+            r = runs[0]
+            prob = {"H": r["H"][1:, 1:], "temperature_K": r["temperature_K"], "depth": r["depth"],
+                    "flags": 0, "baths": [dict(b, state=b["state"] - 1) for b in r["baths"]]}
+            mu3 = np.stack([q["observable"]["mu"][1:] for q in runs])
+            h = heom.Hierarchy(prob, heom.FP64)
+            h.propagate_block(h.block_state(mu3), r["dt_fs"], r["n_steps"], 1, mu3)
+        torch.cuda.synchronize()
+        out[form + "_seconds"] = time.perf_counter() - t0
+        print("absorption: %s form %.3f s" % (form, out[form + "_seconds"]), file=sys.stderr,
+              flush=True)
+    out["bytes_per_ado_full"] = 3 * 8 * 8 * 16
+    out["bytes_per_ado_block"] = 7 * 3 * 16
+    print(json.dumps(out), flush=True)
+
+
 def run_copy(args):
     """A plain device-to-device copy of known size: the reference against
     which the HBM byte counters of a profiler run are scaled."""
@@ -319,6 +352,9 @@ def main():
         return
     if args.workload == "fluorescence":
         run_fluorescence(args)
+        return
+    if args.workload == "absorption":
+        run_absorption(args)
         return
     if args.workload == "serve":
         if args.gpus != 1:

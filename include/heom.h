@@ -228,6 +228,26 @@ heom_status heom_get_state(const heom_hierarchy* h, heom_state s, void* host_sig
 heom_status heom_set_state(const heom_hierarchy* h, heom_state s, const void* host_sigma0,
                            const void* host_rest, void* stream);
 
+/* Linear absorption in the coherence-block form (section "Linear absorption
+ * spectra" with the ground state uncoupled): for the hierarchy `h` of the N
+ * excited states alone (in the frame where the ground energy is 0), each
+ * ADO keeps only its column g, for three directions at once: `state` is
+ * complex128 [n_ado][N][3], Y_u[a][p] = sigma_u^{(p)}[a][g] (start:
+ * Y_0[a][p] = mu_p[a], every other ADO 0).  Classic RK4 in FP64 (the
+ * arrays are 3N complex per ADO instead of 3 (N+1)^2).  Records, every
+ * record_every steps from step 0, the correlations
+ * P_p = sum_a obs[p][a] Y_0[a][p] as [n_rec][6] (Re P_x, Im P_x, ..., Im P_z):
+ * obs = mu gives the absorption correlation of eq. polarization; another
+ * dipole-like vector per direction (e.g. the magnetic term of circular
+ * dichroism) gives the corresponding cross correlation.  `work_dev` holds
+ * heom_block_work_bytes; obs is a host pointer [3][N].  Synchronous.
+ * HEOM_E_UNSTABLE / HEOM_E_NUMERIC as for heom_propagate. */
+size_t heom_block_work_bytes(const heom_info* info, int64_t n_steps, int32_t record_every);
+heom_status heom_propagate_block(const heom_hierarchy* h, void* state, void* work_dev,
+                                 size_t work_bytes, double dt_fs, int64_t n_steps,
+                                 int32_t record_every, const double* obs, double* host_out,
+                                 void* stream);
+
 /* Start of a static fluorescence run (section "Static Fluorescence
  * Spectra"): the dipole operator acts on every ADO of the thermalised
  * hierarchy.  `exc` describes the N excited states alone (its state

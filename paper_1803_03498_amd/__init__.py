@@ -236,6 +236,31 @@ class Hierarchy:
                                     _stream_handle(stream)))
         return rec
 
+    def block_state(self, mu3):
+        """Start of a coherence-block absorption run: complex128 [n_ado, N, 3]
+        on the GPU with Y_0[a][p] = mu3[p][a], every other ADO zero."""
+        torch = _torch()
+        y = torch.zeros((self.n_ado, self.N, 3), dtype=torch.complex128, device="cuda")
+        y[0] = torch.as_tensor(np.asarray(mu3, np.float64).T.astype(np.complex128))
+        return y
+
+    def propagate_block(self, y, dt_fs, n_steps, record_every, obs, stream=None):
+        """heom_propagate_block; returns the correlations P [n_rec, 3] (complex)."""
+        torch = _torch()
+        o = np.ascontiguousarray(obs, dtype=np.float64)
+        if o.shape != (3, self.N):
+            raise ValueError("obs must be [3][N]")
+        info = _info_struct(self.info)
+        nb = load().heom_block_work_bytes(ctypes.byref(info), int(n_steps), int(record_every))
+        work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        n_rec = load().heom_record_count(n_steps, record_every)
+        rec = np.zeros((n_rec, 6))
+        check(load().heom_propagate_block(self.handle, ctypes.c_void_p(y.data_ptr()),
+                                          ctypes.c_void_p(work.data_ptr()), nb, float(dt_fs),
+                                          int(n_steps), int(record_every), o.ctypes.data,
+                                          rec.ctypes.data, _stream_handle(stream)))
+        return rec[:, 0::2] + 1j * rec[:, 1::2]
+
     def get_state(self, state):
         s0, rest = state
         h0 = np.zeros((self.N, self.N), np.complex128)

@@ -123,6 +123,7 @@ struct Derived {
     int64_t n_ado = 0, n_plus = 0;
     int64_t n_low = 0;  // ADOs at levels 1..D-1
     bool h_complex = false;
+    double h_shift = 0.0;            // mean of diag(H) taken off, rad/fs
     std::vector<double> h_re, h_im;  // shifted, rad/fs
     std::vector<int32_t> mode_site;
     std::vector<double> mode_gamma, mode_c_raw, mode_c, mode_lamnu;
@@ -298,6 +299,7 @@ heom_status derive(const heom_problem* p, Derived& d) {
     for (int i = 0; i < N; ++i) mean += hr[(size_t)i * N + i];
     mean /= N;
     for (int i = 0; i < N; ++i) hr[(size_t)i * N + i] -= mean;
+    d.h_shift = mean * kCmToRadFs;
     d.h_re.resize(NN);
     d.h_im.resize(NN);
     for (size_t e = 0; e < NN; ++e) {
@@ -504,6 +506,7 @@ heom_status heom_build_hierarchy(const heom_problem* problem, void* tables_dev,
     t.D = D.D;
     t.n_ado = (int32_t)D.n_ado;
     t.h_complex = D.h_complex ? 1 : 0;
+    t.h_shift = D.h_shift;
     t.h_re = reinterpret_cast<const double*>(base + L.h_re);
     t.h_im = reinterpret_cast<const double*>(base + L.h_im);
     t.h_re_f32 = reinterpret_cast<const float*>(base + L.h_re_f32);
@@ -855,6 +858,63 @@ heom_status heom_timing_read(double* bulk_ms, int64_t* bulk_launches, double* bu
         g_timing.launches = 0;
         g_timing.bytes = 0.0;
     }
+    return HEOM_OK;
+}
+
+size_t heom_block_work_bytes(const heom_info* info, int64_t n_steps, int32_t record_every) {
+    if (!info) return 0;
+    const size_t copy = align256((size_t)info->n_ado * info->n_states * 3 * 16);
+    const size_t rec = align256((size_t)heom_record_count(n_steps, record_every) * 6 * 8);
+    return 256 + 3 * copy + rec;
+}
+
+heom_status heom_propagate_block(const heom_hierarchy* h, void* state, void* work_dev,
+                                 size_t work_bytes, double dt_fs, int64_t n_steps,
+                                 int32_t record_every, const double* obs, double* host_out,
+                                 void* stream) {
+    if (!h || !state || !obs) return fail(HEOM_E_INVAL, "NULL hierarchy, state or obs");
+    if (!aligned(state)) return fail(HEOM_E_INVAL, "state must be 256-byte aligned");
+    if (!is_finite(dt_fs) || !(dt_fs > 0.0)) return fail(HEOM_E_INVAL, "dt must be finite and > 0");
+    if (n_steps < 0 || record_every < 1) return fail(HEOM_E_INVAL, "n_steps < 0 or record_every < 1");
+    const int N = h->t.N;
+    for (int e = 0; e < 3 * N; ++e)
+        if (!is_finite(obs[e])) return fail(HEOM_E_INVAL, "obs[%d] is not finite", e);
+    if (dt_fs * h->d.rate_bound > kRk4RealLimit)
+        return fail(HEOM_E_UNSTABLE, "dt=%g fs times the rate bound %g /fs exceeds %g", dt_fs,
+                    h->d.rate_bound, kRk4RealLimit);
+    const size_t need = heom_block_work_bytes(&h->info, n_steps, record_every);
+    if (!work_dev || work_bytes < need)
+        return fail(HEOM_E_NOMEM, "workspace %zu < %zu bytes", work_bytes, need);
+    if (!aligned(work_dev)) return fail(HEOM_E_INVAL, "work_dev must be 256-byte aligned");
+    char* w = static_cast<char*>(work_dev);
+    int32_t* status = reinterpret_cast<int32_t*>(w);
+    const size_t copy = align256((size_t)h->t.n_ado * N * 3 * 16);
+    void* arr[4] = {state, w + 256, w + 256 + copy, w + 256 + 2 * copy};
+    double* rec = reinterpret_cast<double*>(w + 256 + 3 * copy);
+    const int64_t n_rec = heom_record_count(n_steps, record_every);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemsetAsync(status, 0, 4, st));
+    heom::StageSpec sp[4];
+    heom::rk4_stage_specs(sp);
+    hipError_t e = heom::launch_block_record(state, obs, N, rec, status, st);
+    for (int64_t step = 0; e == hipSuccess && step < n_steps; ++step) {
+        for (int k = 0; k < 4 && e == hipSuccess; ++k) {
+            const void* base[3];
+            for (int m = 0; m < sp[k].nbase; ++m) base[m] = arr[sp[k].base[m]];
+            e = heom::launch_block_stage(h->t, arr[sp[k].in], arr[sp[k].out], base, sp[k].wbase,
+                                         sp[k].nbase, sp[k].w_in, sp[k].hmul * dt_fs, st);
+        }
+        if (e == hipSuccess && (step + 1) % record_every == 0)
+            e = heom::launch_block_record(state, obs, N, rec + 6 * ((step + 1) / record_every),
+                                          status, st);
+    }
+    if (e != hipSuccess) return fail(HEOM_E_DEVICE, "block stage launch: %s", hipGetErrorString(e));
+    int32_t bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, status, 4, hipMemcpyDeviceToHost, st));
+    if (host_out)
+        HIP_TRY(hipMemcpyAsync(host_out, rec, (size_t)n_rec * 6 * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (bad) return fail(HEOM_E_NUMERIC, "a recorded correlation was not finite");
     return HEOM_OK;
 }
 

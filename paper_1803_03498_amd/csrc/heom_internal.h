@@ -21,6 +21,7 @@ __host__ __device__ constexpr int fma_block(int tsize) { return tsize == 4 ? 256
 struct Tables {
     int32_t N, W, D, n_ado;
     int32_t h_complex;            // H has a non-zero imaginary part
+    double h_shift;               // the mean of diag(H) taken off h_re, rad/fs
     const double* h_re;           // [N*N] rad/fs, diagonal shifted by -mean(diag)
     const double* h_im;           // [N*N]
     const float* h_re_f32;        // [N*N] h_re rounded to FP32 (FP32 stage kernels)
@@ -95,6 +96,15 @@ struct StageSpec {
 hipError_t launch_enumerate(const Tables& t, hipStream_t stream);
 // Complex64 copy of the packed ADOs 1..n into `mirror` (Hermitian-packed storage).
 hipError_t launch_pk_mirror(const void* packed_rest, void* mirror, int N, int n, hipStream_t stream);
+// Coherence-block absorption (one RK4 stage over all ADOs, FP64, Y[u][a][p]):
+// out = w_in in + sum_m wb[m] base[m] + h f(in).
+hipError_t launch_block_stage(const Tables& t, const void* in, void* out, const void* const* base,
+                              const double* wb, int nbase, double w_in, double h,
+                              hipStream_t stream);
+// P_p = sum_a obs[p][a] Y_0[a][p] into rec[0..5] (Re, Im per direction);
+// a non-finite value sets *status = 1.
+hipError_t launch_block_record(const void* y, const double* obs, int N, double* rec,
+                               int32_t* status, hipStream_t stream);
 // Fluorescence start: Y_u = sigma_u mu^+ embedded in the (N+1)-state ADOs
 // (precisions 0 = complex128, 1 = complex64 for the bulk of each side).
 hipError_t launch_emission_start(const void* in_sig0, const void* in_rest, int in_prec,

@@ -1566,6 +1566,94 @@ hipError_t launch_pk_mirror(const void* packed_rest, void* mirror, int N, int n,
     return hipGetLastError();
 }
 
+// --------------------------------------------------------------------------
+// Coherence-block form of absorption (section "Linear absorption spectra"):
+// with the ground state g uncoupled from the baths and from the excited
+// states, and sigma_0(0) = mu_p^+ |g><g|, every ADO keeps only its column g
+// on the excited states.  The N x 3 block Y_u[a][p] = sigma_u^{(p)}[a][g]
+// holds the three directions.  Restricted to that column, eq. HEOM reads
+//   f[a][p] = -i (H Y)[a][p] - (gamma_u + Delta_a) Y[a][p]
+//             + sum over "+" modes l of state a of i w_l Y_{u+e_l}[a][p]
+//             + sum over "-" links of state a of (lambda nu + i c) w Y_{u-e_l}[a][p]
+// (V^x and V^o act as the row mask delta_{a,s}; V^x V^x as delta_{a,s};
+// the ground energy is 0 in the frame of the excited block).  FP64, one
+// thread per element, ADO 0 included.
+// --------------------------------------------------------------------------
+struct BlockBases {
+    const void* p[3];
+    double w[3];
+};
+
+__global__ __launch_bounds__(256) void k_block_stage(Tables t, const void* in, void* out,
+                                                     BlockBases bb, int nbase, double w_in,
+                                                     double h, int64_t total) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    const int N = t.N, W = t.W, D = t.D, Dm = D > 0 ? D : 1, R = 3 * N;
+    const int64_t u = idx / R;
+    const int r = (int)(idx - u * R), a = r / 3, p = r - (r / 3) * 3;
+    auto Y = [&](int64_t v, int row) { return ld<double>(in, (size_t)(v * N + row) * 3 + p); };
+    // -i H Y with the diagonal shift restored (the ground energy is 0, so
+    // the shift does not cancel here)
+    double cr = t.h_shift * Y(u, a).re, ci = t.h_shift * Y(u, a).im;
+    for (int b = 0; b < N; ++b) {
+        const double hr = G(t.h_re)[a * N + b], hi = t.h_complex ? G(t.h_im)[a * N + b] : 0.0;
+        const cpx<double> y = Y(u, b);
+        cr += hr * y.re - hi * y.im;
+        ci += hr * y.im + hi * y.re;
+    }
+    const cpx<double> y0 = Y(u, a);
+    const double g = G(t.damping)[u] + G(t.delta_state)[a];
+    double fr = ci - g * y0.re, fi = -cr - g * y0.im;
+    if (G(t.level)[u] < D) {
+        for (int m = G(t.state_mode_begin)[a]; m < G(t.state_mode_begin)[a + 1]; ++m) {
+            const int l = G(t.state_modes)[m];
+            const int nb = G(t.plus)[(size_t)u * W + l];
+            if (nb < 0) continue;
+            const double w = G(t.plus_w)[(size_t)u * W + l];
+            const cpx<double> x = Y(nb, a);
+            fr -= w * x.im;
+            fi += w * x.re;
+        }
+    }
+    for (int k = 0; k < Dm; ++k) {
+        const size_t at = (size_t)u * Dm + k;
+        if (G(t.mlist_site)[at] != a) continue;
+        const int nb = G(reinterpret_cast<const pair_i*>(t.mlist))[at].x;
+        if (nb < 0) continue;
+        const pair_d w = G(reinterpret_cast<const pair_d*>(t.mlist_w))[at];
+        const cpx<double> x = Y(nb, a);
+        fr += w.x * x.re - w.y * x.im;
+        fi += w.x * x.im + w.y * x.re;
+    }
+    double yr = w_in * y0.re + h * fr, yi = w_in * y0.im + h * fi;
+    for (int m = 0; m < nbase; ++m) {
+        const cpx<double> b = ld<double>(bb.p[m], (size_t)idx);
+        yr += bb.w[m] * b.re;
+        yi += bb.w[m] * b.im;
+    }
+    st<double>(out, (size_t)idx, cpx<double>{yr, yi});
+}
+
+struct ObsArg {
+    double v[3][64];
+};
+
+__global__ __launch_bounds__(64) void k_block_record(const void* y, ObsArg obs, int N, double* rec,
+                                                     int32_t* status) {
+    const int p = threadIdx.x;
+    if (p >= 3) return;
+    double pr = 0.0, pi = 0.0;
+    for (int a = 0; a < N; ++a) {
+        const cpx<double> x = ld<double>(y, (size_t)a * 3 + p);
+        pr += obs.v[p][a] * x.re;
+        pi += obs.v[p][a] * x.im;
+    }
+    G(rec)[2 * p] = pr;
+    G(rec)[2 * p + 1] = pi;
+    if (!(isfinite(pr) && isfinite(pi))) *G(status) = 1;
+}
+
 // Fluorescence start (section "Static Fluorescence Spectra": the dipole
 // operator acts on all ADOs): element (i, j) of the (N+1)-state ADO u is
 // sum_b sigma_u[i-1][b] mu[b] for j = 0 < i, zero elsewhere.  One thread per
@@ -1623,6 +1711,31 @@ hipError_t launch_emission_start(const void* in_sig0, const void* in_rest, int i
         hipLaunchKernelGGL((k_emission_start<float, double>), grid, block, 0, stream, in_sig0, in_rest, out_sig0, out_rest, m, N, total);
     else
         hipLaunchKernelGGL((k_emission_start<float, float>), grid, block, 0, stream, in_sig0, in_rest, out_sig0, out_rest, m, N, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_stage(const Tables& t, const void* in, void* out, const void* const* base,
+                              const double* wb, int nbase, double w_in, double h,
+                              hipStream_t stream) {
+    if (nbase < 0 || nbase > 3 || t.N < 1 || t.N > 64) return hipErrorInvalidValue;
+    BlockBases bb{};
+    for (int m = 0; m < nbase; ++m) {
+        bb.p[m] = base[m];
+        bb.w[m] = wb[m];
+    }
+    const int64_t total = (int64_t)t.n_ado * 3 * t.N;
+    hipLaunchKernelGGL(k_block_stage, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream,
+                       t, in, out, bb, nbase, w_in, h, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_record(const void* y, const double* obs, int N, double* rec,
+                               int32_t* status, hipStream_t stream) {
+    if (N < 1 || N > 64) return hipErrorInvalidValue;
+    ObsArg o{};
+    for (int p = 0; p < 3; ++p)
+        for (int a = 0; a < N; ++a) o.v[p][a] = obs[p * N + a];
+    hipLaunchKernelGGL(k_block_record, dim3(1), dim3(64), 0, stream, y, o, N, rec, status);
     return hipGetLastError();
 }
 

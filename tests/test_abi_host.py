@@ -217,3 +217,12 @@ def test_pade_validation(heom):
     assert ei.value.status == -2
     p["baths"][0]["matsubara"] = 64
     assert heom.plan(p)["n_modes"] == 65
+
+
+def test_block_work_bytes(heom):
+    # three copies of n_ado x N x 3 complex128, the records and a status word
+    info = heom._info_struct(heom.plan(hi.fmo_like()))
+    n = 3060 * 7 * 3 * 16
+    copy = (n + 255) // 256 * 256
+    rec = (1001 * 6 * 8 + 255) // 256 * 256
+    assert heom.load().heom_block_work_bytes(ctypes.byref(info), 1000, 1) == 256 + 3 * copy + rec

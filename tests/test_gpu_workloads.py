@@ -93,6 +93,55 @@ def test_fmo_like_pade_low_temperature(heom, orc, T, poles, steps, dt, precision
     assert np.max(np.abs(rec[:, 7] - 1.0)) <= 1e-12
 
 
+# ------------------------------------------ absorption, coherence block ----
+
+def _block_problem(run):
+    """The excited-state problem of a ground + excited absorption run."""
+    return {"H": np.asarray(run["H"])[1:, 1:], "temperature_K": run["temperature_K"],
+            "depth": run["depth"], "flags": run.get("flags", 0),
+            "baths": [dict(b, state=b["state"] - 1) for b in run["baths"]]}
+
+
+def test_fmo_like_absorption_block_form(heom, orc):
+    # the three directions of the FMO-like absorption run in one block
+    # propagation against the oracle's stored full-matrix correlations
+    _case("fmo_like absorption block form")
+    runs = hi.fmo_like_absorption()
+    ref = _golden("fmo_like_absorption_P.txt")
+    P_ref = np.stack([ref[:, 1 + 2 * p] + 1j * ref[:, 2 + 2 * p] for p in range(3)])
+    mu3 = np.stack([r["observable"]["mu"][1:] for r in runs])
+    h = heom.Hierarchy(_block_problem(runs[0]), heom.FP64)
+    P = h.propagate_block(h.block_state(mu3), runs[0]["dt_fs"], runs[0]["n_steps"], 1, mu3).T
+    assert np.max(np.abs(P - P_ref)) <= 1e-12
+    w = np.arange(-1000.0, 1001.0, 1.0)
+    S_ref = orc.spectrum(P_ref, 1.0, w)
+    assert np.max(np.abs(heom.spectrum(P, 1.0, w) - S_ref)) <= 1e-12 * np.max(np.abs(S_ref))
+
+
+@pytest.mark.parametrize("seed,N,M,D", [(1, 2, 0, 4), (2, 3, 1, 3), (3, 5, 1, 2), (4, 4, 2, 2)])
+@pytest.mark.parametrize("cross", [False, True])
+def test_absorption_block_form_random(heom, orc, seed, N, M, D, cross):
+    # against full (N+1)-state oracle runs; cross: observed with another
+    # vector per direction (the form of a circular-dichroism correlation)
+    _case("absorption block form", seed, N, M, D, cross)
+    rng = np.random.default_rng(seed)
+    H = hi.fmo_like_hamiltonian(rng, N)
+    dip = hi.unit_vectors(rng, N)
+    baths = [{"state": s, "lambda_cm": 35.0, "tau_fs": 50.0, "matsubara": M} for s in range(N)]
+    runs = hi.absorption_runs(H, dip, baths, 300.0, D, 1.0, 150)
+    mu3 = np.stack([r["observable"]["mu"][1:] for r in runs])
+    obs3 = rng.normal(size=(3, N)) if cross else mu3
+    P_ref = []
+    for p, r in enumerate(runs):
+        r = dict(r, observable=dict(r["observable"], mu=np.concatenate([[0.0], obs3[p]])))
+        _, rec = orc.run(r)
+        P_ref.append(rec[:, 0] + 1j * rec[:, 1])
+    P_ref = np.stack(P_ref)
+    h = heom.Hierarchy(_block_problem(runs[0]), heom.FP64)
+    P = h.propagate_block(h.block_state(mu3), 1.0, 150, 1, obs3).T
+    assert np.max(np.abs(P - P_ref)) <= 1e-12 * max(1.0, np.max(np.abs(P_ref)))
+
+
 # ------------------------------------------------ static fluorescence ----
 
 def _gpu_fluorescence(heom, relax, emis, prec_exc, prec_full):
