@@ -953,6 +953,22 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute
         const int a = tid / N, c = tid - (tid / N) * N;
         pre = load_nb<T>(nbs, sMnb[a], sMsite[a], c);
     }
+    // The stage bases: with one base they are in flight through the
+    // matrix-core and coupling phases; three would cost registers, so they
+    // are read after the couplings.
+    C bv[NBASE][EPT];
+    if constexpr (NBASE == 1) {
+#pragma unroll
+        for (int m = 0; m < NBASE; ++m) {
+            if (m < sp.nbase) {
+#pragma unroll
+                for (int k = 0; k < EPT; ++k) {
+                    const int i = r0 + RS * k;
+                    bv[m][k] = ld<T>(bptr[m], min(i, N - 1) * N + jc);  // unused outside N x N
+                }
+            }
+        }
+    }
     // 3. X = H [Re S | Im S]: this wave's 16-row block against every column
     //    block, the NB accumulator chains interleaved so that their LDS reads
     //    and matrix-core latencies overlap.
@@ -1117,14 +1133,15 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute
             }
         }
     }
-    C bv[NBASE][EPT];
+    if constexpr (NBASE > 1) {
 #pragma unroll
-    for (int m = 0; m < NBASE; ++m) {
-        if (m < sp.nbase) {
+        for (int m = 0; m < NBASE; ++m) {
+            if (m < sp.nbase) {
 #pragma unroll
-            for (int k = 0; k < EPT; ++k) {
-                const int i = r0 + RS * k;
-                bv[m][k] = ld<T>(bptr[m], min(i, N - 1) * N + jc);  // unused outside N x N
+                for (int k = 0; k < EPT; ++k) {
+                    const int i = r0 + RS * k;
+                    bv[m][k] = ld<T>(bptr[m], min(i, N - 1) * N + jc);  // unused outside N x N
+                }
             }
         }
     }
@@ -1344,6 +1361,21 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<float, NB>())) __attri
             pre = tid < nrn ? pk_nb(nbs, sMnb[a], s, c) : pk_nb(nbs, sMnb[a], c, s);
         }
     }
+    // the stage bases: one base is in flight through the matrix-core phase,
+    // three are read after the couplings (registers)
+    T bv[NBASE][EPT];
+    if constexpr (NBASE == 1) {
+#pragma unroll
+        for (int m = 0; m < NBASE; ++m) {
+            if (m < sp.nbase) {
+#pragma unroll
+                for (int k = 0; k < EPT; ++k) {
+                    const int i = r0 + RS * k;
+                    bv[m][k] = G(bptr[m])[min(i, N - 1) * N + jc];  // unused outside N x N
+                }
+            }
+        }
+    }
     {
         const T* plane = half ? sSim : sSre;
         T* out = half ? sXim : sXre;
@@ -1417,14 +1449,15 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<float, NB>())) __attri
             sQ[i * LX + j] = q;
         }
     }
-    T bv[NBASE][EPT];
+    if constexpr (NBASE > 1) {
 #pragma unroll
-    for (int m = 0; m < NBASE; ++m) {
-        if (m < sp.nbase) {
+        for (int m = 0; m < NBASE; ++m) {
+            if (m < sp.nbase) {
 #pragma unroll
-            for (int k = 0; k < EPT; ++k) {
-                const int i = r0 + RS * k;
-                bv[m][k] = G(bptr[m])[min(i, N - 1) * N + jc];  // unused outside N x N
+                for (int k = 0; k < EPT; ++k) {
+                    const int i = r0 + RS * k;
+                    bv[m][k] = G(bptr[m])[min(i, N - 1) * N + jc];  // unused outside N x N
+                }
             }
         }
     }
