@@ -8,7 +8,7 @@ it only draws Hamiltonians, baths, dipoles, initial states and arrival times.
 Workload shapes follow the paper's light-harvesting examples (Frenkel-exciton
 Hamiltonian, eq. h-ex; one Drude-Lorentz bath per site, eq.
 spectral_density_DL; FMO parameters of Table 1: lambda = 35 cm^-1,
-nu^-1 = 50 fs) and the configurations listed in the design doc.  Every array is
+nu^-1 = 50 fs) and the workload functions below.  Every array is
 drawn from ``numpy.random.default_rng(seed)`` in the order written below.
 
 A problem is a dict::

@@ -12,7 +12,7 @@
 // time-resolved spectroscopy with Distributed Memory HEOM (DM-HEOM)"
 // (arXiv:1803.03498) that it follows.  Section names are the paper's.
 //
-// Conventions (readings of the paper; each is listed in the design doc):
+// Conventions (readings of the paper where it is silent or ambiguous):
 //   * hbar = 1: energies are angular frequencies in rad/fs.  Inputs arrive in
 //     cm^-1, fs and K and are converted here.
 //   * Mode index l = (sum of K_b over earlier baths) + k, 0-based, bath-major;
