@@ -151,7 +151,7 @@ def test_rhs_fp32_mixed(heom, orc, case, herm):
 
 
 # Hermitian-packed FP32 storage: real H, N >= 16 (the matrix-core path)
-PK_CASES = [c for c in RHS_CASES if c[1] >= 16 and not c[5]]
+PK_CASES = [c for c in RHS_CASES if c[1] >= 16 and not c[5].get("complex_h")]
 
 
 @pytest.mark.parametrize("case", PK_CASES, ids=[f"N{c[1]}_B{c[2]}_M{c[3]}_D{c[4]}_{c[0]}"

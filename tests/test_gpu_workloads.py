@@ -137,9 +137,11 @@ def test_absorption_block_form_random(heom, orc, seed, N, M, D, cross):
         _, rec = orc.run(r)
         P_ref.append(rec[:, 0] + 1j * rec[:, 1])
     P_ref = np.stack(P_ref)
-    h = heom.Hierarchy(_block_problem(runs[0]), heom.FP64)
-    P = h.propagate_block(h.block_state(mu3), 1.0, 150, 1, obs3).T
-    assert np.max(np.abs(P - P_ref)) <= 1e-12 * max(1.0, np.max(np.abs(P_ref)))
+    # the block path is FP64 whatever precision the hierarchy was built for
+    for prec in (heom.FP64, heom.FP32_MIXED):
+        h = heom.Hierarchy(_block_problem(runs[0]), prec)
+        P = h.propagate_block(h.block_state(mu3), 1.0, 150, 1, obs3).T
+        assert np.max(np.abs(P - P_ref)) <= 1e-12 * max(1.0, np.max(np.abs(P_ref)))
 
 
 # ------------------------------------------------ static fluorescence ----
