@@ -248,6 +248,15 @@ heom_status heom_propagate_block(const heom_hierarchy* h, void* state, void* wor
                                  int32_t record_every, const double* obs, double* host_out,
                                  void* stream);
 
+/* Host only: the excitation vectors of circular dichroism (eq.
+ * CDdipoleoperator, section "Circular dichroism spectra"):
+ *   m[p][a] = (R_a x d_a) . e_p,  p = x, y, z,
+ * for pigment centres R [N][3] and transition dipoles d [N][3] (any
+ * consistent units).  A coherence-block run started from m (Y_0[a][p] =
+ * m[p][a]) and observed with the dipoles (obs[p][a] = d_a . e_p) gives the
+ * rotationally averaged CD correlation through heom_spectrum. */
+heom_status heom_cd_vectors(const double* R, const double* d, int32_t n_sites, double* m);
+
 /* Start of a static fluorescence run (section "Static Fluorescence
  * Spectra"): the dipole operator acts on every ADO of the thermalised
  * hierarchy.  `exc` describes the N excited states alone (its state

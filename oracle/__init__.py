@@ -209,6 +209,12 @@ def emission_start(state, mu):
     return Y
 
 
+def cd_vectors(R, d):
+    """Excitation vectors of circular dichroism (eq. CDdipoleoperator):
+    m[p][a] = (R_a x d_a) . e_p."""
+    return np.cross(np.asarray(R, np.float64), np.asarray(d, np.float64)).T.copy()
+
+
 def fluorescence(relax, emis):
     """Oracle fluorescence pipeline: relax the excited-state hierarchy from
     its Boltzmann start, then propagate sigma_u(inf) mu_p^+ for each

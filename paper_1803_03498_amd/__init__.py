@@ -17,7 +17,7 @@ import numpy as np
 from . import _abi
 from ._abi import FP32_HERM, FP32_MIXED, FP64, OBS_DIPOLE, OBS_POPULATION, HeomError, check, load
 
-__all__ = ["FP64", "FP32_MIXED", "FP32_HERM", "problem_coefficients", "emission_start", "pack_hermitian", "unpack_hermitian", "OBS_POPULATION", "OBS_DIPOLE", "HeomError", "Problem", "plan",
+__all__ = ["FP64", "FP32_MIXED", "FP32_HERM", "problem_coefficients", "emission_start", "cd_vectors", "pack_hermitian", "unpack_hermitian", "OBS_POPULATION", "OBS_DIPOLE", "HeomError", "Problem", "plan",
            "Hierarchy", "Server", "spectrum", "load"]
 
 
@@ -274,6 +274,18 @@ class Hierarchy:
         hr = np.ascontiguousarray(host_rest, dtype=self._host_rest_dtype)
         check(load().heom_set_state(self.handle, self._st(state), h0.ctypes.data,
                                     hr.ctypes.data if hr.size else None, _stream_handle()))
+
+
+def cd_vectors(R, d):
+    """heom_cd_vectors: m [3][N], m[p][a] = (R_a x d_a) . e_p (host only)."""
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    n = R.shape[0]
+    if R.shape != (n, 3) or d.shape != (n, 3):
+        raise ValueError("R and d must be [N][3]")
+    m = np.zeros((3, n))
+    check(load().heom_cd_vectors(R.ctypes.data, d.ctypes.data, n, m.ctypes.data))
+    return m
 
 
 def emission_start(h_exc, state_exc, h_full, state_full, mu, stream=None):

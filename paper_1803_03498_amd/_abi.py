@@ -85,6 +85,7 @@ SIGNATURES = {
     "heom_problem_coefficients": (i32, [vp, vp, vp, vp, vp]),
     "heom_emission_start": (i32, [vp, HeomState, vp, HeomState, vp, vp]),
     "heom_block_work_bytes": (sz, [vp, i64, i32]),
+    "heom_cd_vectors": (i32, [vp, vp, i32, vp]),
     "heom_propagate_block": (i32, [vp, vp, vp, sz, f64, i64, i32, vp, vp, vp]),
     "heom_rhs": (i32, [vp, HeomState, HeomState, i32, vp]),
     "heom_propagate": (i32, [vp, HeomState, vp, sz, f64, i64, i32, P(HeomObservable), i32, vp,

@@ -861,6 +861,21 @@ heom_status heom_timing_read(double* bulk_ms, int64_t* bulk_launches, double* bu
     return HEOM_OK;
 }
 
+heom_status heom_cd_vectors(const double* R, const double* d, int32_t n_sites, double* m) {
+    if (!R || !d || !m || n_sites < 1) return fail(HEOM_E_INVAL, "NULL array or n_sites < 1");
+    for (int a = 0; a < n_sites; ++a) {
+        const double* r = R + 3 * a;
+        const double* v = d + 3 * a;
+        const double c[3] = {r[1] * v[2] - r[2] * v[1], r[2] * v[0] - r[0] * v[2],
+                             r[0] * v[1] - r[1] * v[0]};
+        for (int p = 0; p < 3; ++p) {
+            if (!is_finite(c[p])) return fail(HEOM_E_INVAL, "site %d: non-finite R or d", a);
+            m[p * n_sites + a] = c[p];
+        }
+    }
+    return HEOM_OK;
+}
+
 size_t heom_block_work_bytes(const heom_info* info, int64_t n_steps, int32_t record_every) {
     if (!info) return 0;
     const size_t copy = align256((size_t)info->n_ado * info->n_states * 3 * 16);

@@ -226,3 +226,10 @@ def test_block_work_bytes(heom):
     copy = (n + 255) // 256 * 256
     rec = (1001 * 6 * 8 + 255) // 256 * 256
     assert heom.load().heom_block_work_bytes(ctypes.byref(info), 1000, 1) == 256 + 3 * copy + rec
+
+
+def test_cd_vectors_match_oracle(heom, orc):
+    rng = np.random.default_rng(4)
+    R = rng.normal(size=(9, 3)) * 10
+    d = rng.normal(size=(9, 3))
+    assert np.allclose(heom.cd_vectors(R, d), orc.cd_vectors(R, d), rtol=1e-15, atol=1e-14)

@@ -144,6 +144,30 @@ def test_absorption_block_form_random(heom, orc, seed, N, M, D, cross):
         assert np.max(np.abs(P - P_ref)) <= 1e-12 * max(1.0, np.max(np.abs(P_ref)))
 
 
+def test_cd_block_form(heom, orc):
+    # circular dichroism: the block run started from the rotational vectors
+    # m_p and observed with the dipoles, against full-matrix oracle runs
+    _case("cd block form")
+    rng = np.random.default_rng(12)
+    R = hi.aggregate_geometry(rng, 5)
+    d = hi.unit_vectors(rng, 5)
+    H = hi.dipole_couplings(R, d) + np.diag(rng.normal(12400.0, 100.0, 5))
+    baths = [{"state": s, "lambda_cm": 35.0, "tau_fs": 50.0, "matsubara": 1} for s in range(5)]
+    runs = hi.absorption_runs(H, d, baths, 300.0, 3, 1.0, 200)
+    m = heom.cd_vectors(R, d)
+    P_ref = []
+    for p, r in enumerate(runs):
+        rho0 = np.zeros_like(r["rho0"])
+        rho0[1:, 0] = m[p]
+        _, rec = orc.run(dict(r, rho0=rho0))
+        P_ref.append(rec[:, 0] + 1j * rec[:, 1])
+    P_ref = np.stack(P_ref)
+    mu3 = np.stack([r["observable"]["mu"][1:] for r in runs])
+    h = heom.Hierarchy(_block_problem(runs[0]), heom.FP64)
+    P = h.propagate_block(h.block_state(m), 1.0, 200, 1, mu3).T
+    assert np.max(np.abs(P - P_ref)) <= 1e-12 * np.max(np.abs(P_ref))
+
+
 # ------------------------------------------------ static fluorescence ----
 
 def _gpu_fluorescence(heom, relax, emis, prec_exc, prec_full):

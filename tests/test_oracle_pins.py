@@ -506,6 +506,39 @@ def test_fluorescence_lambda_zero_closed_form(orc):
         assert np.max(np.abs(P[k] - ref)) < 1e-12
 
 
+def _cd_correlation(orc, H, R, d, T=300.0, D=3, steps=200):
+    """Full (N+1)-state oracle runs: start m_p^+ |g><g|, observe mu_p."""
+    baths = [{"state": s, "lambda_cm": 35.0, "tau_fs": 50.0, "matsubara": 0}
+             for s in range(H.shape[0])]
+    runs = hi.absorption_runs(H, d, baths, T, D, 1.0, steps)
+    m = orc.cd_vectors(R, d)
+    P = []
+    for p, r in enumerate(runs):
+        rho0 = np.zeros_like(r["rho0"])
+        rho0[1:, 0] = m[p]
+        _, rec = orc.run(dict(r, rho0=rho0))
+        P.append(rec[:, 0] + 1j * rec[:, 1])
+    return np.stack(P)
+
+
+def test_cd_conservative_and_origin_independent(orc):
+    # eq. CDdipoleoperator: sum_p m_p . mu_p = sum_a (R_a x d_a) . d_a = 0, so
+    # the averaged CD correlation starts at 0 (the spectrum integrates to 0);
+    # shifting every R_a by one vector c adds sum_ab c . (d_a x d_b) G_ab(t),
+    # which vanishes because the block propagator is symmetric in the sites
+    rng = np.random.default_rng(9)
+    R = hi.aggregate_geometry(rng, 3)
+    d = hi.unit_vectors(rng, 3)
+    H = hi.dipole_couplings(R, d) + np.diag(rng.normal(12400.0, 100.0, 3))
+    m = orc.cd_vectors(R, d)
+    assert np.allclose(m[:, 0], np.cross(R[0], d[0]), rtol=0, atol=1e-14)
+    P = _cd_correlation(orc, H, R, d)
+    scale = np.max(np.abs(P))
+    assert abs(P[:, 0].sum()) <= 1e-13 * scale
+    P2 = _cd_correlation(orc, H, R + np.array([3.0, -7.0, 11.0]), d)
+    assert np.max(np.abs(P.sum(axis=0) - P2.sum(axis=0))) <= 1e-11 * scale
+
+
 def test_dipole_correlation_lambda_zero(orc):
     # lambda = 0: P_p(t) = sum_e |e_p . D_e|^2 exp(-i eps_e t) over excitons.
     runs = hi.fmo_like_absorption(n_steps=200)
