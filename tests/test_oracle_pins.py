@@ -506,6 +506,22 @@ def test_fluorescence_lambda_zero_closed_form(orc):
         assert np.max(np.abs(P[k] - ref)) < 1e-12
 
 
+def test_absorption_stays_in_the_coherence_block(orc):
+    # the closure behind the coherence-block form: with the ground state
+    # uncoupled, a full absorption run keeps every ADO zero outside its
+    # (e, g) column (exactly: the other entries never receive a contribution)
+    rng = np.random.default_rng(21)
+    H = hi.fmo_like_hamiltonian(rng, 4)
+    d = hi.unit_vectors(rng, 4)
+    baths = [{"state": s, "lambda_cm": 35.0, "tau_fs": 50.0, "matsubara": 1} for s in range(4)]
+    run = hi.absorption_runs(H, d, baths, 300.0, 3, 1.0, 100)[1]
+    st, _ = orc.run(run)
+    mask = np.zeros(st.shape[1:], bool)
+    mask[1:, 0] = True
+    assert np.max(np.abs(st[:, mask])) > 1e-3
+    assert np.max(np.abs(st[:, ~mask])) == 0.0
+
+
 def _cd_correlation(orc, H, R, d, T=300.0, D=3, steps=200):
     """Full (N+1)-state oracle runs: start m_p^+ |g><g|, observe mu_p."""
     baths = [{"state": s, "lambda_cm": 35.0, "tau_fs": 50.0, "matsubara": 0}
