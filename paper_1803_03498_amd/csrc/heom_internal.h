@@ -12,9 +12,15 @@ namespace heom {
 
 constexpr int kMaxStates = 64;
 constexpr int kBlock = 256;
-// Threads of an FMA-path stage workgroup: FP32 256, FP64 64 (its registers
-// allow fewer waves per SIMD, and smaller workgroups fill them better).
-__host__ __device__ constexpr int fma_block(int tsize) { return tsize == 4 ? 256 : 64; }
+// Threads of an FMA-path stage workgroup: FP32 256; FP64 64 (its registers
+// allow fewer waves per SIMD, and smaller workgroups fill them better),
+// except for N^2 <= 64, where 64 threads would hold a single ADO with idle
+// lanes and 256 hold several.  The kernel loops over its tile's elements with
+// the launch's block size, so any of these is correct for any tile.
+constexpr int kFmaMaxBlock = 256;
+__host__ __device__ constexpr int fma_block(int tsize, int N) {
+    return (tsize == 4 || N * N <= 64) ? 256 : 64;
+}
 
 // Device pointers into the caller's tables buffer, plus the scalars the
 // kernels need.  Everything here is written once by heom_build_hierarchy.

@@ -519,7 +519,9 @@ constexpr int kPrefRows = 4;
 
 // --------------------------------------------------------------------------
 // Bulk stage kernel, wavefront-FMA path (N < 16, or complex H): a workgroup
-// of fma_block threads takes GA = max(1, fma_block / N^2) consecutive ADOs;
+// of fma_block threads takes GA = max(1, fma_block / N^2) consecutive ADOs
+// (computed per job by the host; a batched launch uses the block size of its
+// largest N, and the element loops stride by the launch's block size);
 // every thread owns whole matrix elements.  Each ADO's link rows (the
 // compact "-" list with its states and weights, the "+" neighbours and
 // weights) are copied to LDS first from the precomputed tables, so an
@@ -529,7 +531,7 @@ constexpr int kPrefRows = 4;
 // HC: some job of the launch has a complex H (otherwise H is real).
 // --------------------------------------------------------------------------
 template <typename T, bool BATCHED, bool HC>
-__global__ __launch_bounds__(fma_block(sizeof(T))) __attribute__((amdgpu_waves_per_eu(
+__global__ __launch_bounds__(kFmaMaxBlock) __attribute__((amdgpu_waves_per_eu(
     sizeof(T) == 4 ? 8 : 5))) void k_bulk_fma(Job single, const Job* jobs, int n_jobs, StageSpec sp,
                                               int s0_blocks, unsigned lds_total) {
     extern __shared__ char smem_raw[];
@@ -1584,7 +1586,7 @@ int bulk_mfma_blocks(int N, bool h_complex, int precision) {
 
 int bulk_ados_per_tile(int N, int W, int D, int tsize) {
     const int NN = N * N;
-    const int nt = fma_block(tsize);
+    const int nt = fma_block(tsize, N);
     int g = NN >= nt ? 1 : nt / NN;
     // keep a tile's LDS (matrices plus staged links) within 64 KiB
     while (g > 1 && fma_lds(N, W, D, g, tsize).total > 64 * 1024) --g;
@@ -1945,7 +1947,7 @@ static hipError_t launch_fma_t(const Job& single, const Job* jobs_dev, int n_job
     hipError_t e = sigma0_ride_along<T, BATCHED>(single, jobs_dev, n_jobs, n_s0, sizeof(T) == 4, sp,
                                                  160 * 1024 / 8, stream, &extra, &lds_launch);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_bulk_fma<T, BATCHED, HC>), dim3(total_tiles + extra), dim3(fma_block(sizeof(T))),
+    hipLaunchKernelGGL((k_bulk_fma<T, BATCHED, HC>), dim3(total_tiles + extra), dim3(fma_block(sizeof(T), single.t.N)),
                        lds_launch, stream, single, jobs_dev, n_jobs, sp, extra, (unsigned)lds_launch);
     return hipGetLastError();
 }
