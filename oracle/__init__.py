@@ -173,10 +173,17 @@ def record_size(N, kind):
     return N + 3 if kind == KIND_POPULATION else 4
 
 
-def propagate(prob, state, dt_fs, n_steps, record_every=1, observable=None):
-    """Textbook RK4.  Returns (final state, records [n_rec][record_size])."""
+def propagate(prob, state, dt_fs, n_steps, record_every=1, observable=None, inplace=False):
+    """Textbook RK4.  Returns (final state, records [n_rec][record_size]).
+    With ``inplace`` a C-contiguous complex128 ``state`` is advanced in place
+    (no copy: large hierarchies need every gigabyte)."""
     pk = _Packed(prob)
-    x = np.array(state, dtype=np.complex128, order="C", copy=True)
+    if inplace:
+        x = state
+        if x.dtype != np.complex128 or not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("inplace propagation needs a C-contiguous complex128 array")
+    else:
+        x = np.array(state, dtype=np.complex128, order="C", copy=True)
     obs = observable or {"kind": "population"}
     kind = KIND_POPULATION if obs["kind"] == "population" else KIND_DIPOLE
     mu = np.ascontiguousarray(obs.get("mu", np.zeros(pk.N)), dtype=np.float64)

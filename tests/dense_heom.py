@@ -41,8 +41,13 @@ def modes_of(prob, orc):
     return modes, baths
 
 
-def liouvillian(prob, orc, rescale=True, terminator=True, gauge=1.0):
-    H = np.asarray(prob["H"], dtype=np.complex128) * TWO_PI_C
+def liouvillian(prob, orc, rescale=True, terminator=True, gauge=1.0, add_reorg=False):
+    H = np.array(prob["H"], dtype=np.complex128)
+    if add_reorg:
+        # eq. h-ex: the site energy carries the reorganisation energy of its bath
+        for b in prob["baths"]:
+            H[b["state"], b["state"]] += b["lambda_cm"]
+    H = H * TWO_PI_C
     N = H.shape[0]
     D = prob["depth"]
     modes, baths = modes_of(prob, orc)

@@ -233,3 +233,10 @@ def test_cd_vectors_match_oracle(heom, orc):
     R = rng.normal(size=(9, 3)) * 10
     d = rng.normal(size=(9, 3))
     assert np.allclose(heom.cd_vectors(R, d), orc.cd_vectors(R, d), rtol=1e-15, atol=1e-14)
+
+
+def test_cd_vectors_literal_orientation(heom):
+    # eq. CDdipoleoperator: m_p = (R_a x d_a) . e_p, with x cross y = z etc.
+    R = np.array([[1.0, 0, 0], [0, 2.0, 0], [0, 0, 3.0], [4.0, 0, 0]])
+    d = np.array([[0, 1.0, 0], [0, 0, 1.0], [1.0, 0, 0], [2.0, 0, 0]])
+    assert np.array_equal(heom.cd_vectors(R, d), [[0, 2, 0, 0], [0, 0, 3, 0], [1, 0, 0, 0]])

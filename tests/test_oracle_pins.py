@@ -296,7 +296,10 @@ def test_rhs_flags_match_dense(orc):
     prob = hi.random_problem(6, 3, M=1, D=2)
     N = 3
     for flags, kw in ((hi.FLAG_NO_TERMINATOR, {"terminator": False}),
-                      (hi.FLAG_STANDARD_GAUGE, {"gauge": -1.0})):
+                      (hi.FLAG_STANDARD_GAUGE, {"gauge": -1.0}),
+                      (hi.FLAG_ADD_REORG, {"add_reorg": True}),
+                      (hi.FLAG_ADD_REORG | hi.FLAG_NO_TERMINATOR,
+                       {"add_reorg": True, "terminator": False})):
         p = dict(prob, flags=flags)
         L, tups = dense_heom.liouvillian(p, orc, **kw)
         x = hi.random_state(12, len(tups), N)
@@ -578,3 +581,115 @@ def test_dipole_correlation_lambda_zero(orc):
         # and R^n tracks the exact exp(-i eps t) to the RK4 truncation error
         Pex = (amp[None, :] * np.exp(-1j * np.outer(n * r["dt_fs"], w))).sum(axis=1)
         assert np.max(np.abs(P - Pex)) < 1e-5
+
+
+# ------------------------------------------------- records, CD, c_k < 0 ----
+
+def test_record_known_residual_trace_and_polarisation(orc):
+    # the observables of sigma_0 on a state with known values: populations,
+    # trace, max_ij |rho_ij - conj(rho_ji)| and P = sum_a mu_a rho[a][g]
+    prob = hi.dimer()
+    rho = np.array([[0.6, 0.3 + 0.1j], [0.5 - 0.2j, 0.4 + 0.05j]])
+    W, n = orc.sizes(prob)
+    _, rec = orc.propagate(prob, orc.initial_state(prob, n, rho), 1.0, 0, 1)
+    # (0,1): 0.3+0.1i - (0.5+0.2i) = -0.2-0.1i, |.| = sqrt(0.05); (1,1): 0.1i
+    assert np.array_equal(rec[0, :4], [0.6, 0.4, 1.0, 0.05])
+    assert abs(rec[0, 4] - 0.22360679774997896) < 1e-16
+    obs = {"kind": "dipole", "mu": np.array([2.0, -1.5]), "ground": 1}
+    _, rec = orc.propagate(prob, orc.initial_state(prob, n, rho), 1.0, 0, 1, obs)
+    # 2 (0.3+0.1i) - 1.5 (0.4+0.05i) = 0 + 0.125i
+    assert abs(rec[0, 0] - 0.0) < 1e-15 and abs(rec[0, 1] - 0.125) < 1e-15
+    assert np.array_equal(rec[0, 2:4], [1.0, 0.05])
+
+
+def test_cd_vectors_literal_orientation(orc):
+    # eq. CDdipoleoperator: m_p = (R_a x d_a) . e_p; x cross y = z, y cross z = x,
+    # z cross x = y, and a dipole along R gives nothing
+    R = np.array([[1.0, 0, 0], [0, 2.0, 0], [0, 0, 3.0], [4.0, 0, 0]])
+    d = np.array([[0, 1.0, 0], [0, 0, 1.0], [1.0, 0, 0], [2.0, 0, 0]])
+    m = orc.cd_vectors(R, d)
+    assert m.shape == (3, 4)
+    assert np.array_equal(m, [[0, 2, 0, 0], [0, 0, 3, 0], [1, 0, 0, 0]])
+
+
+def test_cd_correlation_lambda_zero_closed_form(orc):
+    # lambda = 0: the run started from m_p^+|g><g| and observed with d_p gives
+    # P_p(n dt) = sum_e (d_p . phi_e)(m_p . phi_e) R(-i eps_e dt)^n, R the RK4
+    # stability polynomial; m and d enter in different roles, so exchanging
+    # them in the start vector or the observable changes the result's sign
+    rng = np.random.default_rng(31)
+    R = hi.aggregate_geometry(rng, 3)
+    d = hi.unit_vectors(rng, 3)
+    H = hi.dipole_couplings(R, d) + np.diag(rng.normal(12400.0, 100.0, 3))
+    baths = [{"state": s, "lambda_cm": 0.0, "tau_fs": 50.0, "matsubara": 0} for s in range(3)]
+    runs = hi.absorption_runs(H, d, baths, 300.0, 1, 1.0, 150)
+    m = orc.cd_vectors(R, d)
+    for p, r in enumerate(runs):
+        rho0 = np.zeros_like(r["rho0"])
+        rho0[1:, 0] = m[p]
+        _, rec = orc.run(dict(r, rho0=rho0))
+        w, v = np.linalg.eigh(r["H"][1:, 1:] * TWO_PI_C)
+        amp = (v.T @ d[:, p]) * (v.T @ m[p])
+        z = -1j * w * r["dt_fs"]
+        Rz = 1 + z + z**2 / 2 + z**3 / 6 + z**4 / 24
+        n = np.arange(len(rec))
+        ref = (amp[None, :] * Rz[None, :] ** n[:, None]).sum(axis=1)
+        assert np.max(np.abs(rec[:, 0] + 1j * rec[:, 1] - ref)) < 1e-12 * max(1.0, np.abs(amp).sum())
+
+
+def _low_t_bath():
+    # 10 K, nu^-1 = 20 fs: the first Matsubara rate 2 pi k_B T / hbar
+    # (0.0082 / fs) lies below nu (0.05 / fs), so c_1 < 0
+    return {"lambda_cm": 20.0, "tau_fs": 20.0, "matsubara": 1}, 10.0
+
+
+def test_negative_weight_bath_dense_liouvillian(orc):
+    b, T = _low_t_bath()
+    g, c, _, _ = orc.bath_coefficients(b["lambda_cm"], b["tau_fs"], T, b["matsubara"])
+    assert c[1] < 0 < c[0] and g[1] < g[0]
+    prob = hi.random_problem(17, 3, M=1, D=2)
+    prob["temperature_K"] = T
+    prob["baths"] = [dict(b, state=s) for s in range(3)]
+    for flags in (0, hi.FLAG_NO_RESCALE):
+        p = dict(prob, flags=flags)
+        L, tups = dense_heom.liouvillian(p, orc, rescale=not flags)
+        x = hi.random_state(18, len(tups), 3)
+        f = orc.rhs(p, x)
+        ref = (L @ x.reshape(-1)).reshape(x.shape)
+        assert np.max(np.abs(f - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_negative_weight_bath_rescaling_invariance(orc):
+    # sigma_0 must not depend on the |c|-rescaling when some c_k < 0
+    b, T = _low_t_bath()
+    prob = hi.random_problem(19, 3, M=1, D=3)
+    prob["temperature_K"] = T
+    prob["baths"] = [dict(b, state=s) for s in range(3)]
+    W, n = orc.sizes(prob)
+    rho0 = hi.population_rho0(3, 2)
+    base, _ = orc.propagate(prob, orc.initial_state(prob, n, rho0), 1.0, 200, 200)
+    p = dict(prob, flags=hi.FLAG_NO_RESCALE)
+    y, _ = orc.propagate(p, orc.initial_state(p, n, rho0), 1.0, 200, 200)
+    assert np.max(np.abs(base[0])) > 0.1
+    assert np.max(np.abs(y[0] - base[0])) < 1e-13
+
+
+def test_negative_weight_bath_pure_dephasing_cumulant(orc):
+    # the second-cumulant closed form of the pure-dephasing test with a bath
+    # whose Matsubara weight is negative
+    b, T = _low_t_bath()
+    eps = 100.0
+    prob = {"H": np.diag([0.0, eps]), "temperature_K": T, "depth": 12, "flags": 0,
+            "baths": [dict(b, state=1)]}
+    W, n = orc.sizes(prob)
+    g, c, lamnu, delta = orc.bath_coefficients(b["lambda_cm"], b["tau_fs"], T, b["matsubara"])
+    ct = c.astype(complex)
+    ct[0] -= 1j * lamnu
+    s = orc.initial_state(prob, n, np.full((2, 2), 0.5, complex))
+    t = 0.0
+    for _ in range(4):
+        s, _ = orc.propagate(prob, s, 0.5, 100, 100)
+        t += 50.0
+        gt = np.sum(ct / g**2 * (g * t - 1 + np.exp(-g * t))) + delta * t
+        ref = 0.5 * np.exp(-1j * eps * TWO_PI_C * t - gt)
+        assert abs(s[0][1, 0] - ref) < 1e-9
