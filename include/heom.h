@@ -221,6 +221,22 @@ heom_status heom_propagate(const heom_hierarchy* h, heom_state io, void* work_de
                            const heom_observable* obs, int32_t hermitian, double* host_out,
                            void* stream);
 
+/* heom_propagate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the workspace is the library's static device scratch, one 64 MiB array per
+ * GPU held until the process ends, instead of a caller buffer.  Same
+ * arguments, results and errors as heom_propagate otherwise; the step counter,
+ * status word and records in the scratch are rewritten at every call.
+ * HEOM_E_NOMEM if heom_propagate_work_bytes exceeds 64 MiB (three stage copies
+ * of the state plus the records).  Allocates nothing (no hipMalloc/hipFree,
+ * no events).  All calls on one GPU share its scratch: calls that overlap on
+ * one GPU (from several threads or streams) race and must be serialised by
+ * the caller; a call is complete when it returns (it synchronises). */
+heom_status heom_propagate_noalloc(const heom_hierarchy* h, heom_state io, double dt_fs,
+                                   int64_t n_steps, int32_t record_every,
+                                   const heom_observable* obs, int32_t hermitian,
+                                   double* host_out, void* stream);
+
 /* Checkpoint / resume of a state: synchronous device <-> host copies of
  * sigma_0 (complex128 [N][N]) and the ADOs u >= 1 (element type by precision). */
 heom_status heom_get_state(const heom_hierarchy* h, heom_state s, void* host_sigma0,

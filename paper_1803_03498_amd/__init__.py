@@ -236,6 +236,23 @@ class Hierarchy:
                                     _stream_handle(stream)))
         return rec
 
+    def propagate_noalloc(self, state, dt_fs, n_steps, record_every=1, observable=None,
+                          hermitian=False, stream=None):
+        """heom_propagate_noalloc (workspace in the library's static device
+        scratch); returns the records [n_rec, record_doubles] (numpy)."""
+        obs = observable or {"kind": "population"}
+        kind = OBS_POPULATION if obs["kind"] == "population" else OBS_DIPOLE
+        mu = np.ascontiguousarray(obs.get("mu", np.zeros(self.N)), dtype=np.float64)
+        o = _abi.HeomObservable(kind, int(obs.get("ground", 0)),
+                                mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        n_rec = load().heom_record_count(n_steps, record_every)
+        rec = np.zeros((n_rec, load().heom_record_doubles(self.N, kind)))
+        check(load().heom_propagate_noalloc(self.handle, self._st(state), float(dt_fs),
+                                            int(n_steps), int(record_every), ctypes.byref(o),
+                                            1 if hermitian else 0, rec.ctypes.data,
+                                            _stream_handle(stream)))
+        return rec
+
     def block_state(self, mu3):
         """Start of a coherence-block absorption run: complex128 [n_ado, N, 3]
         on the GPU with Y_0[a][p] = mu3[p][a], every other ADO zero."""

@@ -90,6 +90,8 @@ SIGNATURES = {
     "heom_rhs": (i32, [vp, HeomState, HeomState, i32, vp]),
     "heom_propagate": (i32, [vp, HeomState, vp, sz, f64, i64, i32, P(HeomObservable), i32, vp,
                              vp]),
+    "heom_propagate_noalloc": (i32, [vp, HeomState, f64, i64, i32, P(HeomObservable), i32, vp,
+                                     vp]),
     "heom_get_state": (i32, [vp, HeomState, vp, vp, vp]),
     "heom_set_state": (i32, [vp, HeomState, vp, vp, vp]),
     "heom_destroy": (i32, [vp]),

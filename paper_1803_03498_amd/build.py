@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libheom.so")
 SOURCES = [os.path.join(CSRC, "heom_kernels.hip"), os.path.join(CSRC, "heom_host.cpp"),
-           os.path.join(CSRC, "heom_server.cpp")]
+           os.path.join(CSRC, "heom_server.cpp"), os.path.join(CSRC, "heom_scratch.hip")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

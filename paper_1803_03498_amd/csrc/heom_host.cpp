@@ -744,10 +744,16 @@ heom_status heom_rhs(const heom_hierarchy* h, heom_state in, heom_state out, int
     return HEOM_OK;
 }
 
-heom_status heom_propagate(const heom_hierarchy* h, heom_state io, void* work_dev,
+}  // extern "C"
+
+namespace {
+
+// heom_propagate on a given workspace.  `timing` allows the benchmark event
+// timing (which creates HIP events); the no-alloc entry point passes false.
+heom_status propagate_impl(const heom_hierarchy* h, heom_state io, void* work_dev,
                            size_t work_bytes, double dt_fs, int64_t n_steps, int32_t record_every,
                            const heom_observable* obs, int32_t hermitian, double* host_out,
-                           void* stream) {
+                           void* stream, bool timing) {
     if (!h) return fail(HEOM_E_INVAL, "hierarchy is NULL");
     heom_status s;
     if ((s = check_state(h, io, "io")) != HEOM_OK) return s;
@@ -776,10 +782,11 @@ heom_status heom_propagate(const heom_hierarchy* h, heom_state io, void* work_de
                                        kind == HEOM_OBS_DIPOLE ? obs->ground : 0, hermitian);
 
     hipStream_t st = static_cast<hipStream_t>(stream);
-    // control block: step = 0, status = 0, mu
-    std::vector<char> ctl(heom::control_bytes(N), 0);
-    if (kind == HEOM_OBS_DIPOLE) std::memcpy(ctl.data() + 1024, obs->mu, N * 8);
-    HIP_TRY(hipMemcpyAsync(w, ctl.data(), ctl.size(), hipMemcpyHostToDevice, st));
+    // control block: step = 0, status = 0, mu (N <= 64: at most 1536 bytes)
+    alignas(16) char ctl[1024 + 64 * 8] = {};
+    const size_t ctl_bytes = std::min(heom::control_bytes(N), sizeof(ctl));
+    if (kind == HEOM_OBS_DIPOLE) std::memcpy(ctl + 1024, obs->mu, N * 8);
+    HIP_TRY(hipMemcpyAsync(w, ctl, ctl_bytes, hipMemcpyHostToDevice, st));
 
     heom::StageSpec sp[4];
     heom::rk4_stage_specs(sp);
@@ -795,7 +802,7 @@ heom_status heom_propagate(const heom_hierarchy* h, heom_state io, void* work_de
             sp[k].mirror_out = 2 - (k & 1);
         }
     }
-    const bool timed = g_timing.enabled.load() && tiles > 0;
+    const bool timed = timing && g_timing.enabled.load() && tiles > 0;
     std::vector<hipEvent_t> ev;
     if (timed) {
         ev.resize(2 * (size_t)n_steps * 4);
@@ -840,6 +847,42 @@ heom_status heom_propagate(const heom_hierarchy* h, heom_state io, void* work_de
     }
     if (status) return fail(HEOM_E_NUMERIC, "non-finite observable");
     return HEOM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+heom_status heom_propagate(const heom_hierarchy* h, heom_state io, void* work_dev,
+                           size_t work_bytes, double dt_fs, int64_t n_steps, int32_t record_every,
+                           const heom_observable* obs, int32_t hermitian, double* host_out,
+                           void* stream) {
+    return propagate_impl(h, io, work_dev, work_bytes, dt_fs, n_steps, record_every, obs,
+                          hermitian, host_out, stream, true);
+}
+
+heom_status heom_propagate_noalloc(const heom_hierarchy* h, heom_state io, double dt_fs,
+                                   int64_t n_steps, int32_t record_every,
+                                   const heom_observable* obs, int32_t hermitian,
+                                   double* host_out, void* stream) {
+    if (!h) return fail(HEOM_E_INVAL, "hierarchy is NULL");
+    if (n_steps < 0 || record_every < 1) return fail(HEOM_E_INVAL, "n_steps < 0 or record_every < 1");
+    const int kind = obs ? obs->kind : HEOM_OBS_POPULATION;
+    if (kind != HEOM_OBS_POPULATION && kind != HEOM_OBS_DIPOLE)
+        return fail(HEOM_E_INVAL, "observable kind %d unknown", kind);
+    const size_t need = heom_propagate_work_bytes(&h->info, n_steps, record_every, kind);
+    if (need > heom::kScratchBytes)
+        return fail(HEOM_E_NOMEM,
+                    "workspace of %zu bytes exceeds the library's static scratch (%zu bytes); "
+                    "use heom_propagate with a caller workspace",
+                    need, heom::kScratchBytes);
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    hipError_t e = heom::scratch_buffer(&scratch, &scratch_bytes);
+    if (e != hipSuccess)
+        return fail(HEOM_E_DEVICE, "static scratch lookup: %s", hipGetErrorString(e));
+    return propagate_impl(h, io, scratch, scratch_bytes, dt_fs, n_steps, record_every, obs,
+                          hermitian, host_out, stream, false);
 }
 
 heom_status heom_timing_enable(int32_t enable) {

@@ -11,6 +11,8 @@
 namespace heom {
 
 constexpr int kMaxStates = 64;
+// Size of the library's static device scratch (heom_propagate_noalloc).
+constexpr size_t kScratchBytes = size_t(64) << 20;
 constexpr int kBlock = 256;
 // Threads of an FMA-path stage workgroup: FP32 256; FP64 64 (its registers
 // allow fewer waves per SIMD, and smaller workgroups fill them better),
@@ -144,6 +146,9 @@ __host__ __device__ inline FmaLds fma_lds(int N, int W, int D, int GA, int tsize
 
 // ADOs per FMA-path tile: fma_block / N^2 threads' worth, reduced to fit 64 KiB of LDS.
 int bulk_ados_per_tile(int N, int W, int D, int tsize);
+// Device address and size of this device's static scratch array (looked up
+// once per device, with that device current; thread-safe).
+hipError_t scratch_buffer(void** out, size_t* bytes);
 // Name of the kernel whose launch failed in the last launch_stage call on this thread.
 const char* last_launch_failure();
 // Which bulk kernel a job uses: 0 = FMA path, otherwise 16*nb >= N on the MFMA path.
