@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 
 #include "heom_internal.h"
 
@@ -1199,6 +1201,8 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute
 }
 
 
+#include "heom_stage_persist.inc"
+
 // Bulk RK4 stage on Hermitian-packed FP32 storage (P as defined at pk_nb).
 // Same thread layout and matrix-core product as k_bulk_mfma on its
 // Hermitian path; the sigma planes are unpacked from P in LDS.  In P-space
@@ -1897,6 +1901,69 @@ static hipError_t launch_mfma(int nb, bool herm, const Job& single, const Job* j
 }
 
 
+// Workgroups of the persistent kernel that are resident at once on the
+// device (all MI355X CUs alike), cached per kernel and LDS size.
+static int resident_workgroups(const void* fn, int threads, size_t lds) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    static std::atomic<int> n_cu{0};
+    if (n_cu.load() == 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus < 1)
+            cus = 256;
+        n_cu.store(cus);
+    }
+    return per_cu * n_cu.load();
+}
+
+template <int NB, int NBASE>
+static hipError_t launch_persist_t(const Job& single, int total_tiles, const StageSpec& sp,
+                                   hipStream_t stream) {
+    const void* fn = reinterpret_cast<const void*>(&k_stage_persist<NB, NBASE>);
+    static std::once_flag attr_once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(attr_once, [&] {
+        attr_err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    });
+    if (attr_err != hipSuccess) return attr_err;
+    constexpr int NT = 128 * NB;
+    const size_t own = PersistLds<NB>::bytes;
+    // sigma_0 rides along when its staging fits the LDS that the register
+    // limit leaves to each resident workgroup
+    int by_regs = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&by_regs, fn, NT, own) != hipSuccess || by_regs < 1)
+        by_regs = 1;
+    const size_t budget = std::max(own, (size_t)(160 * 1024 / by_regs) & ~(size_t)1023);
+    size_t lds = own;
+    int extra = 0;
+    hipError_t e = sigma0_ride_along<float, false>(single, nullptr, 1, 1, true, sp, budget, stream,
+                                                   &extra, &lds);
+    if (e != hipSuccess) return e;
+    const int workers = std::min(total_tiles, resident_workgroups(fn, NT, lds));
+    hipLaunchKernelGGL((k_stage_persist<NB, NBASE>), dim3(extra + workers), dim3(NT), lds, stream,
+                       single, sp, total_tiles, extra, (unsigned)lds);
+    return hipGetLastError();
+}
+
+template <int NB>
+static hipError_t launch_persist_nb(const Job& single, int total_tiles, const StageSpec& sp,
+                                    hipStream_t stream) {
+    if (sp.nbase == 0) return launch_persist_t<NB, 0>(single, total_tiles, sp, stream);
+    if (sp.nbase == 1) return launch_persist_t<NB, 1>(single, total_tiles, sp, stream);
+    return launch_persist_t<NB, 3>(single, total_tiles, sp, stream);
+}
+
+// The persistent kernel takes single-job FP32 stages over Hermitian ADOs
+// with a real H and an even N of 16..64.
+static bool persist_applies(const Job& single, bool batched, int nb) {
+    return !batched && single.herm != 0 && nb >= 1 && nb <= 4 && (single.t.N % 2) == 0 &&
+           single.t.h_complex == 0;
+}
+
 template <int NB, int NBASE>
 static hipError_t launch_mfma_pk_t(const Job& single, int total_tiles, const StageSpec& sp,
                                    hipStream_t stream) {
@@ -1976,8 +2043,18 @@ static hipError_t launch_stage_t(const Job& single, const Job* jobs_dev, int n_j
     const int nb = bulk_mfma_blocks(N, single.t.h_complex != 0, sizeof(T) == 8 ? 0 : 1);
     if (nb > 0) {
         if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
-        e = launch_mfma<T>(nb, single.herm != 0, single, jobs_dev, n_jobs, total_tiles, sp, stream, n_s0);
-        if (e != hipSuccess) g_launch_what = "MFMA bulk stage kernel";
+        if (sizeof(T) == 4 && persist_applies(single, batched, nb)) {
+            switch (nb) {
+                case 1: e = launch_persist_nb<1>(single, total_tiles, sp, stream); break;
+                case 2: e = launch_persist_nb<2>(single, total_tiles, sp, stream); break;
+                case 3: e = launch_persist_nb<3>(single, total_tiles, sp, stream); break;
+                default: e = launch_persist_nb<4>(single, total_tiles, sp, stream); break;
+            }
+            if (e != hipSuccess) g_launch_what = "persistent MFMA stage kernel";
+        } else {
+            e = launch_mfma<T>(nb, single.herm != 0, single, jobs_dev, n_jobs, total_tiles, sp, stream, n_s0);
+            if (e != hipSuccess) g_launch_what = "MFMA bulk stage kernel";
+        }
     } else {
         if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
         // batched launches carry the largest tile LDS of the batch
