@@ -257,7 +257,11 @@ heom_status heom_set_state(const heom_hierarchy* h, heom_state s, const void* ho
  * dipole-like vector per direction (e.g. the magnetic term of circular
  * dichroism) gives the corresponding cross correlation.  `work_dev` holds
  * heom_block_work_bytes; obs is a host pointer [3][N].  Synchronous.
- * HEOM_E_UNSTABLE / HEOM_E_NUMERIC as for heom_propagate. */
+ * HEOM_E_UNSTABLE as for heom_propagate, with the mean of diag(H) added to
+ * the rate bound (a single column keeps it), and also when that mean times
+ * dt exceeds 0.5 rad: give the excited block in a frame rotating near the
+ * excited energies (subtract their mean).  HEOM_E_NUMERIC as for
+ * heom_propagate. */
 size_t heom_block_work_bytes(const heom_info* info, int64_t n_steps, int32_t record_every);
 heom_status heom_propagate_block(const heom_hierarchy* h, void* state, void* work_dev,
                                  size_t work_bytes, double dt_fs, int64_t n_steps,

@@ -46,6 +46,9 @@ heom_status fail(heom_status s, const char* fmt, ...) {
 constexpr double kCmToRadFs = 2.0 * M_PI * 2.99792458e-5;
 constexpr double kBoltzmannCm = 0.6950348004;
 constexpr double kRk4RealLimit = 2.78;  // RK4 stability interval on the negative real axis
+// Largest phase per step of the diagonal offset kept by the coherence-block
+// form: RK4 advances e^{-i w dt} with relative error ~ (w dt)^5 / 120, 3e-4 at 0.5.
+constexpr double kBlockPhaseLimit = 0.5;
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // one complex64 copy of n ADOs of N x N
@@ -937,9 +940,17 @@ heom_status heom_propagate_block(const heom_hierarchy* h, void* state, void* wor
     const int N = h->t.N;
     for (int e = 0; e < 3 * N; ++e)
         if (!is_finite(obs[e])) return fail(HEOM_E_INVAL, "obs[%d] is not finite", e);
-    if (dt_fs * h->d.rate_bound > kRk4RealLimit)
-        return fail(HEOM_E_UNSTABLE, "dt=%g fs times the rate bound %g /fs exceeds %g", dt_fs,
-                    h->d.rate_bound, kRk4RealLimit);
+    // A single column keeps the mean of diag(H) (the frame's offset from the
+    // ground energy): it adds |h_shift| to the rate bound, and more than
+    // kBlockPhaseLimit of phase per step means H was not given in a frame
+    // rotating near the excited energies.
+    const double shift = std::fabs(h->d.h_shift);
+    if (dt_fs * (h->d.rate_bound + shift) > kRk4RealLimit || dt_fs * shift > kBlockPhaseLimit)
+        return fail(HEOM_E_UNSTABLE,
+                    "dt=%g fs: rate bound %g /fs with the diagonal offset %g rad/fs of H (limits: "
+                    "%g for the bound, %g rad per step for the offset; give the excited block in a "
+                    "frame rotating at the mean excited energy)",
+                    dt_fs, h->d.rate_bound + shift, shift, kRk4RealLimit, kBlockPhaseLimit);
     const size_t need = heom_block_work_bytes(&h->info, n_steps, record_every);
     if (!work_dev || work_bytes < need)
         return fail(HEOM_E_NOMEM, "workspace %zu < %zu bytes", work_bytes, need);

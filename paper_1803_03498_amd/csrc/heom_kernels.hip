@@ -1792,16 +1792,21 @@ hipError_t launch_enumerate(const Tables& t, hipStream_t stream) {
     return hipGetLastError();
 }
 
+// Lets kernel `fn` take up to 160 KiB of LDS.  Called once per kernel (the
+// launcher's own once_flag), so concurrent first launches do not race.
+static hipError_t allow_full_lds(std::once_flag& once, hipError_t& err, const void* fn) {
+    std::call_once(once, [&] {
+        err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    });
+    return err;
+}
+
 template <typename T, bool BATCHED, bool PK = false>
 static hipError_t launch_sigma0_t(const Job& single, const Job* jobs_dev, int n_jobs,
                                   const StageSpec& sp, size_t lds, hipStream_t stream) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sigma0<T, BATCHED, PK>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (a != hipSuccess) return a;
-        attr_set = true;
-    }
+    static std::once_flag attr_once;
+    static hipError_t attr_err = hipSuccess;
+    if (allow_full_lds(attr_once, attr_err, reinterpret_cast<const void*>(&k_sigma0<T, BATCHED, PK>)) != hipSuccess) return attr_err;
     hipLaunchKernelGGL((k_sigma0<T, BATCHED, PK>), dim3(BATCHED ? n_jobs : 1), dim3(kBlock), lds,
                        stream, single, jobs_dev, n_jobs, sp, (unsigned)lds);
     return hipGetLastError();
@@ -1822,8 +1827,8 @@ static hipError_t sigma0_ride_along(const Job& single, const Job* jobs_dev, int 
     // largest N and W of the batch; non-Hermitian staging needs the most LDS
     const size_t full = sigma0_lds(N, W, (int)sizeof(T), false, 160 * 1024).total;
     const size_t bare = sigma0_lds(N, W, (int)sizeof(T), false, 0).total;
-    if (allow && (full <= cap || bare <= *lds)) {
-        if (full <= cap) *lds = std::max(*lds, full);
+    if (allow && bare <= cap) {
+        *lds = std::max(*lds, full <= cap ? full : bare);
         *added = n_s0;
         return hipSuccess;
     }
@@ -1835,13 +1840,9 @@ template <typename T, int NB, bool HERM, bool BATCHED, int NBASE>
 static hipError_t launch_mfma_t(const Job& single, const Job* jobs_dev, int n_jobs,
                                 int total_tiles, const StageSpec& sp, hipStream_t stream, int n_s0) {
     const void* fn = reinterpret_cast<const void*>(&k_bulk_mfma<T, NB, HERM, BATCHED, NBASE>);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t a =
-            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (a != hipSuccess) return a;
-        attr_set = true;
-    }
+    static std::once_flag attr_once;
+    static hipError_t attr_err = hipSuccess;
+    if (allow_full_lds(attr_once, attr_err, fn) != hipSuccess) return attr_err;
     constexpr int AW = mfma_ados_per_wg<T, NB>();
     const unsigned stride =
         (unsigned)((MfmaLds<T, NB, HERM>::bytes(single.t.N, single.t.W, single.t.D) + 15) & ~(size_t)15);
@@ -1926,10 +1927,7 @@ static hipError_t launch_persist_t(const Job& single, int total_tiles, const Sta
     const void* fn = reinterpret_cast<const void*>(&k_stage_persist<NB, NBASE>);
     static std::once_flag attr_once;
     static hipError_t attr_err = hipSuccess;
-    std::call_once(attr_once, [&] {
-        attr_err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    });
-    if (attr_err != hipSuccess) return attr_err;
+    if (allow_full_lds(attr_once, attr_err, fn) != hipSuccess) return attr_err;
     constexpr int NT = 128 * NB;
     const size_t own = PersistLds<NB>::bytes;
     // sigma_0 rides along when its staging fits the LDS that the register
@@ -1968,13 +1966,9 @@ template <int NB, int NBASE>
 static hipError_t launch_mfma_pk_t(const Job& single, int total_tiles, const StageSpec& sp,
                                    hipStream_t stream) {
     const void* fn = reinterpret_cast<const void*>(&k_bulk_mfma_pk<NB, NBASE>);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t a =
-            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (a != hipSuccess) return a;
-        attr_set = true;
-    }
+    static std::once_flag attr_once;
+    static hipError_t attr_err = hipSuccess;
+    if (allow_full_lds(attr_once, attr_err, fn) != hipSuccess) return attr_err;
     constexpr int AW = mfma_ados_per_wg<float, NB>();
     const unsigned stride =
         (unsigned)((MfmaLds<float, NB, true>::bytes(single.t.N, single.t.W, single.t.D) + 15) & ~(size_t)15);
@@ -2000,13 +1994,9 @@ template <typename T, bool BATCHED, bool HC>
 static hipError_t launch_fma_t(const Job& single, const Job* jobs_dev, int n_jobs,
                                int total_tiles, const StageSpec& sp, size_t lds,
                                hipStream_t stream, int n_s0) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bulk_fma<T, BATCHED, HC>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (a != hipSuccess) return a;
-        attr_set = true;
-    }
+    static std::once_flag attr_once;
+    static hipError_t attr_err = hipSuccess;
+    if (allow_full_lds(attr_once, attr_err, reinterpret_cast<const void*>(&k_bulk_fma<T, BATCHED, HC>)) != hipSuccess) return attr_err;
     // FP32 only: the FP64 sigma_0 code would cost the FP64 kernel its
     // occupancy.  Eight FP32 workgroups per CU leave 20 KiB of LDS each.
     int extra = 0;

@@ -191,8 +191,18 @@ void heom_server::fail_all(const char* what, hipError_t e) {
 void heom_server::fail_all_locked(const char* what, hipError_t e) {
     fatal = HEOM_E_DEVICE;
     fatal_msg = std::string(what) + ": " + hipGetErrorString(e);
-    for (Req* r : active) finish(r, HEOM_E_DEVICE);
-    for (Req* r : draining) finish(r, HEOM_E_DEVICE);
+    // Work already enqueued (kernels, record copies) may still touch the
+    // requests' ranges: let the stream drain before they are freed and the
+    // results published (the error itself may make this return early).
+    (void)hipStreamSynchronize(stream);
+    for (Req* r : active) {
+        release_resources(r);
+        finish(r, HEOM_E_DEVICE);
+    }
+    for (Req* r : draining) {
+        release_resources(r);
+        finish(r, HEOM_E_DEVICE);
+    }
     for (Req* r : pending) finish(r, HEOM_E_DEVICE);
     active.clear();
     draining.clear();

@@ -102,6 +102,23 @@ def _block_problem(run):
             "baths": [dict(b, state=b["state"] - 1) for b in run["baths"]]}
 
 
+def test_block_form_refuses_unrotated_frame(heom):
+    # excited energies ~12300 cm^-1 above a ground state at 0 (no rotating
+    # frame): the column keeps that offset, 2.3 rad per 1-fs step
+    run = hi.fmo_like_absorption(n_steps=10)[0]
+    prob = _block_problem(run)
+    prob["H"] = prob["H"] + 12300.0 * np.eye(7)
+    mu3 = np.stack([r["observable"]["mu"][1:] for r in hi.fmo_like_absorption(n_steps=10)])
+    h = heom.Hierarchy(prob, heom.FP64)
+    with pytest.raises(heom.HeomError) as e:
+        h.propagate_block(h.block_state(mu3), 1.0, 10, 1, mu3)
+    assert e.value.status == -6
+    # the same block in the rotating frame is accepted
+    h2 = heom.Hierarchy(_block_problem(run), heom.FP64)
+    P = h2.propagate_block(h2.block_state(mu3), 1.0, 10, 1, mu3)
+    assert np.all(np.isfinite(P))
+
+
 def test_fmo_like_absorption_block_form(heom, orc):
     # the three directions of the FMO-like absorption run in one block
     # propagation against the oracle's stored full-matrix correlations
