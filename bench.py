@@ -96,6 +96,8 @@ def parse():
     ap.add_argument("--precision", default="fp32_mixed", choices=["fp32_mixed", "fp32_herm", "fp64"])
     ap.add_argument("--cpu-baseline-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample (0 disables it)")
+    ap.add_argument("--no-fp64-check", action="store_true",
+                    help="skip the untimed FP64 run of the same steps")
     ap.add_argument("--serve-requests", type=int, default=128)
     ap.add_argument("--serve-steps", type=int, default=1000)
     ap.add_argument("--serve-load", type=float, default=0.8)
@@ -134,10 +136,72 @@ def cpu_baseline(prob, target_s):
     per_rhs = max(dt, 1e-9) / k
     return {"value": 1.0 / (4.0 * per_rhs), "unit": "ADO-updates/s", "cores": 1,
             "kind": "oracle",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "threads_available": len(os.sched_getaffinity(0)),
             "sample": "FP64 oracle right-hand side of the last %d ADOs (depth-%d level) of %s, "
-                      "%.1f s of CPU; one ADO-update = 4 evaluations; model setup (%.1f s) "
-                      "excluded; host %s" % (k, prob["depth"], prob.get("name", "?"), dt, t_setup,
-                                             platform.processor() or platform.machine())}
+                      "%.1f s of CPU on one thread; one ADO-update = 4 evaluations; model "
+                      "setup (%.1f s) excluded" % (k, prob["depth"], prob.get("name", "?"), dt,
+                                                   t_setup)}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def _bulk_kernel_name(info, precision, N, heom):
+    """The stage kernel that propagates ADOs u >= 1 of a Hermitian run."""
+    if precision == heom.FP32_MIXED and 10 <= N <= 64:
+        return "k_stage_persist"
+    if not info["bulk_kernel"]:
+        return "k_bulk_fma"
+    return "k_bulk_mfma_pk" if precision == heom.FP32_HERM else "k_bulk_mfma"
+
+
+def _fp64_reference(heom, torch, lib, prob, precision, steps, rec_every, N, n):
+    """The benchmarked steps from the initial state in FP64 (timed, with its
+    bulk-kernel events) and in `precision`; returns the FP64 figures and the
+    largest population difference over the records."""
+    out = {}
+    recs = {}
+    for prec in (heom.FP64, precision):
+        h = heom.Hierarchy(prob, prec)
+        st = h.new_state(prob["rho0"])
+        work = h.workspace(steps, rec_every, heom.OBS_POPULATION)
+        torch.cuda.synchronize()
+        if prec == heom.FP64:
+            lib.heom_timing_enable(1)
+            lib.heom_timing_read(None, None, None, 1)
+        t0 = time.perf_counter()
+        recs[prec] = h.propagate(st, prob["dt_fs"], steps, rec_every, hermitian=True, work=work)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        if prec == heom.FP64:
+            lib.heom_timing_enable(0)
+            ms = ctypes.c_double()
+            launches = ctypes.c_int64()
+            kbytes = ctypes.c_double()
+            lib.heom_timing_read(ctypes.byref(ms), ctypes.byref(launches), ctypes.byref(kbytes), 1)
+            avg = ms.value / 1e3 / max(launches.value, 1)
+            achieved = kbytes.value / max(launches.value, 1) / avg / 1e9
+            out.update({"ms_per_step": 1e3 * el / steps, "ado_updates_per_s": n * steps / el,
+                        "bulk_kernel": _bulk_kernel_name(h.info, prec, N, heom),
+                        "avg_launch_ms": avg * 1e3, "achieved_GBps": achieved,
+                        "frac": achieved / HBM_PEAK_GBS, "steps": steps,
+                        "note": "complex128 throughout, same workload, untimed in the line's value"})
+        del st, work, h
+        torch.cuda.empty_cache()
+    a, b = recs[heom.FP64], recs[precision]
+    out["fp32_vs_fp64_max_population_error"] = float(np.max(np.abs(a[:, :N] - b[:, :N])))
+    out["fp32_trace_drift"] = float(np.max(np.abs(b[:, N] - 1.0)))
+    out["records_compared"] = int(a.shape[0])
+    return out
 
 
 def _percentile(xs, q):
@@ -405,7 +469,7 @@ def main():
     kbytes = ctypes.c_double()
     lib.heom_timing_read(ctypes.byref(ms), ctypes.byref(launches), ctypes.byref(kbytes), 1)
 
-    kernel_short = "k_bulk_mfma" if info["bulk_kernel"] else "k_bulk_fma"
+    kernel_short = _bulk_kernel_name(info, precision, N, heom)
     kernel_name = kernel_short + " (RK4 stage, ADOs u>=1)"
     traffic = measured_traffic(kernel_short, args.workload, args.precision)
     elapsed = t1 - t0
@@ -423,6 +487,17 @@ def main():
                                         achieved, rec[-1, N]), file=sys.stderr, flush=True)
     if not np.all(np.isfinite(pops)):
         raise RuntimeError("non-finite populations")
+
+    # untimed: the same steps from the initial state in FP64 (timed on its
+    # own) and again in the benchmarked precision, for the error of the
+    # reduced-precision result against FP64
+    fp64 = None
+    if precision != heom.FP64 and not args.no_fp64_check:
+        del work
+        fp64 = _fp64_reference(heom, torch, lib, prob, precision, steps, rec_every, N, n)
+        print("FP64 %.3f ms/step; FP32 vs FP64 max population error %.3e" % (
+            fp64["ms_per_step"], fp64["fp32_vs_fp64_max_population_error"]), file=sys.stderr,
+            flush=True)
 
     cpu = None
     if args.cpu_baseline_seconds > 0:
@@ -464,6 +539,7 @@ def main():
             "bytes_per_launch_algorithmic": bytes_per_launch,
         },
         "cpu_baseline": cpu,
+        "fp64": fp64,
     }
     print(json.dumps(line), flush=True)
 

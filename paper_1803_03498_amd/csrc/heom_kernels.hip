@@ -1904,11 +1904,12 @@ static hipError_t launch_mfma(int nb, bool herm, const Job& single, const Job* j
 
 // Workgroups of the persistent kernel that are resident at once on the
 // device (all MI355X CUs alike), cached per kernel and LDS size.
-static int resident_workgroups(const void* fn, int threads, size_t lds) {
+static int resident_workgroups(const void* fn, int threads, size_t lds, int max_per_cu) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
+    per_cu = std::min(per_cu, max_per_cu);
     static std::atomic<int> n_cu{0};
     if (n_cu.load() == 0) {
         int dev = 0, cus = 0;
@@ -1921,10 +1922,10 @@ static int resident_workgroups(const void* fn, int threads, size_t lds) {
     return per_cu * n_cu.load();
 }
 
-template <int NB, int NBASE>
+template <int NB, int NBASE, int VEC>
 static hipError_t launch_persist_t(const Job& single, int total_tiles, const StageSpec& sp,
                                    hipStream_t stream) {
-    const void* fn = reinterpret_cast<const void*>(&k_stage_persist<NB, NBASE>);
+    const void* fn = reinterpret_cast<const void*>(&k_stage_persist<NB, NBASE, VEC>);
     static std::once_flag attr_once;
     static hipError_t attr_err = hipSuccess;
     if (allow_full_lds(attr_once, attr_err, fn) != hipSuccess) return attr_err;
@@ -1932,34 +1933,55 @@ static hipError_t launch_persist_t(const Job& single, int total_tiles, const Sta
     const size_t own = PersistLds<NB>::bytes;
     // sigma_0 rides along when its staging fits the LDS that the register
     // limit leaves to each resident workgroup
+    // two workers per CU for N > 32 (measured faster than the three that the
+    // registers of the stage without bases allow)
+    const int cap = NB >= 3 ? 2 : 16;
     int by_regs = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&by_regs, fn, NT, own) != hipSuccess || by_regs < 1)
         by_regs = 1;
+    by_regs = std::min(by_regs, cap);
     const size_t budget = std::max(own, (size_t)(160 * 1024 / by_regs) & ~(size_t)1023);
     size_t lds = own;
     int extra = 0;
     hipError_t e = sigma0_ride_along<float, false>(single, nullptr, 1, 1, true, sp, budget, stream,
                                                    &extra, &lds);
     if (e != hipSuccess) return e;
-    const int workers = std::min(total_tiles, resident_workgroups(fn, NT, lds));
-    hipLaunchKernelGGL((k_stage_persist<NB, NBASE>), dim3(extra + workers), dim3(NT), lds, stream,
-                       single, sp, total_tiles, extra, (unsigned)lds);
+    const int workers = std::min(total_tiles, resident_workgroups(fn, NT, lds, cap));
+    hipLaunchKernelGGL((k_stage_persist<NB, NBASE, VEC>), dim3(extra + workers), dim3(NT), lds,
+                       stream, single, sp, total_tiles, extra, (unsigned)lds);
     return hipGetLastError();
+}
+
+template <int NB, int VEC>
+static hipError_t launch_persist_vec(const Job& single, int total_tiles, const StageSpec& sp,
+                                     hipStream_t stream) {
+    switch (sp.nbase) {
+        case 0: return launch_persist_t<NB, 0, VEC>(single, total_tiles, sp, stream);
+        case 1: return launch_persist_t<NB, 1, VEC>(single, total_tiles, sp, stream);
+        case 2: return launch_persist_t<NB, 2, VEC>(single, total_tiles, sp, stream);
+        case 3: return launch_persist_t<NB, 3, VEC>(single, total_tiles, sp, stream);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int NB>
 static hipError_t launch_persist_nb(const Job& single, int total_tiles, const StageSpec& sp,
                                     hipStream_t stream) {
-    if (sp.nbase == 0) return launch_persist_t<NB, 0>(single, total_tiles, sp, stream);
-    if (sp.nbase == 1) return launch_persist_t<NB, 1>(single, total_tiles, sp, stream);
-    return launch_persist_t<NB, 3>(single, total_tiles, sp, stream);
+    // even N: element pairs (aligned 16-byte accesses); odd N: single elements
+    return single.t.N % 2 == 0 ? launch_persist_vec<NB, 2>(single, total_tiles, sp, stream)
+                               : launch_persist_vec<NB, 1>(single, total_tiles, sp, stream);
 }
 
 // The persistent kernel takes single-job FP32 stages over Hermitian ADOs
-// with a real H and an even N of 16..64.
-static bool persist_applies(const Job& single, bool batched, int nb) {
-    return !batched && single.herm != 0 && nb >= 1 && nb <= 4 && (single.t.N % 2) == 0 &&
-           single.t.h_complex == 0;
+// with a real H and 10 <= N <= 64.  Below N = 10 an ADO fills too little of
+// a 16 x 16 matrix-core tile, and the FMA kernel's tiles of several ADOs are
+// faster (measured at N = 7: 15.9 against 17.8 ms per launch on the 12.3M-ADO
+// (6, 6) FMO reference; at N = 14, 1.18 against 0.40 ms on 237k ADOs).
+static int persist_blocks(const Job& single, bool batched) {
+    if (batched || single.herm == 0 || single.t.h_complex != 0 || single.t.N < 10 ||
+        single.t.N > 64)
+        return 0;
+    return (single.t.N + 15) / 16;
 }
 
 template <int NB, int NBASE>
@@ -2030,21 +2052,30 @@ static hipError_t launch_stage_t(const Job& single, const Job* jobs_dev, int n_j
     // MFMA path for 16 <= N (real H); FP64 above N = 48 would need more than
     // 160 KiB of LDS and stays on the FMA path.  sigma_0 rides along with the
     // bulk launch where its LDS fits.
+    const int pb = sizeof(T) == 4 ? persist_blocks(single, batched) : 0;
+    if (pb > 0) {
+        // one tile per ADO u >= 1 (the job's tile count may group small ADOs
+        // for the FMA kernel)
+        const int n_ados = single.t.n_ado - 1;
+        if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
+        switch (pb) {
+            case 1: e = launch_persist_nb<1>(single, n_ados, sp, stream); break;
+            case 2: e = launch_persist_nb<2>(single, n_ados, sp, stream); break;
+            case 3: e = launch_persist_nb<3>(single, n_ados, sp, stream); break;
+            default: e = launch_persist_nb<4>(single, n_ados, sp, stream); break;
+        }
+        if (e != hipSuccess) {
+            g_launch_what = "persistent MFMA stage kernel";
+            return e;
+        }
+        if (ev_end) e = hipEventRecord(ev_end, stream);
+        return e;
+    }
     const int nb = bulk_mfma_blocks(N, single.t.h_complex != 0, sizeof(T) == 8 ? 0 : 1);
     if (nb > 0) {
         if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
-        if (sizeof(T) == 4 && persist_applies(single, batched, nb)) {
-            switch (nb) {
-                case 1: e = launch_persist_nb<1>(single, total_tiles, sp, stream); break;
-                case 2: e = launch_persist_nb<2>(single, total_tiles, sp, stream); break;
-                case 3: e = launch_persist_nb<3>(single, total_tiles, sp, stream); break;
-                default: e = launch_persist_nb<4>(single, total_tiles, sp, stream); break;
-            }
-            if (e != hipSuccess) g_launch_what = "persistent MFMA stage kernel";
-        } else {
-            e = launch_mfma<T>(nb, single.herm != 0, single, jobs_dev, n_jobs, total_tiles, sp, stream, n_s0);
-            if (e != hipSuccess) g_launch_what = "MFMA bulk stage kernel";
-        }
+        e = launch_mfma<T>(nb, single.herm != 0, single, jobs_dev, n_jobs, total_tiles, sp, stream, n_s0);
+        if (e != hipSuccess) g_launch_what = "MFMA bulk stage kernel";
     } else {
         if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
         // batched launches carry the largest tile LDS of the batch
