@@ -56,11 +56,17 @@ def _mix_largest():
     return run
 
 
+KERNEL_SOURCES = ("heom_kernels.hip", "heom_stage_persist.inc")
+
+
 def _kernel_source_digest():
+    """SHA-256 over the device sources, in the order of KERNEL_SOURCES."""
     import hashlib
-    src = os.path.join(ROOT, "paper_1803_03498_amd", "csrc", "heom_kernels.hip")
-    with open(src, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1803_03498_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel, workload, precision):
