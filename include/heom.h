@@ -340,7 +340,18 @@ typedef struct {
     const double* rho0;     /* host complex128 [n_runs][N][N]         */
     heom_observable obs;    /* mu: [n_runs][N] for dipole runs        */
     int32_t hermitian;      /* the initial state is Hermitian         */
+    int32_t form;           /* HEOM_FORM_*: how the server may run it  */
 } heom_request;
+
+/* heom_request.form.  AUTO lets the server run an eligible dipole request in
+ * the coherence-block form (as heom_propagate_block, FP64): at most three
+ * runs, the ground state `obs.ground` without a bath and without coupling in
+ * H, each initial state zero outside column `ground` (rows != ground), and a
+ * step that passes the block form's step check.  Its records keep the
+ * layout of the full form: [Re P, Im P, Re Tr, Im Tr] with Tr = 0 exactly.
+ * FULL always propagates the full density matrices in the request's
+ * precision. */
+enum { HEOM_FORM_AUTO = 0, HEOM_FORM_FULL = 1, HEOM_FORM_BLOCK = 2 /* reported only */ };
 
 typedef struct {
     heom_status status;     /* HEOM_OK, HEOM_PENDING or an error       */
@@ -351,6 +362,8 @@ typedef struct {
     double t_submit_s;      /* host monotonic clock, seconds           */
     double t_admit_s;
     double t_finish_s;
+    int32_t form;           /* HEOM_FORM_FULL or HEOM_FORM_BLOCK: the form
+                               the server chose at submission            */
 } heom_result;
 
 /* Create a server on one device stream.  arena_dev/arena_bytes is caller-owned

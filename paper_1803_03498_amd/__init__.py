@@ -332,9 +332,10 @@ class Server:
         self.handle = h
         self._keep = {}
 
-    def submit(self, runs, precision=FP32_MIXED, hermitian=None):
+    def submit(self, runs, precision=FP32_MIXED, hermitian=None, form=0):
         """Submit runs (list of run dicts sharing one problem, see heom_inputs)
-        as one request; returns its ticket."""
+        as one request; returns its ticket.  form: 0 = the server may use the
+        coherence-block form for eligible dipole runs, 1 = full matrices."""
         r0 = runs[0]
         prob = Problem(r0, precision)
         N = prob.N
@@ -349,7 +350,7 @@ class Server:
                                float(r0["dt_fs"]), rho0.ctypes.data_as(dp),
                                _abi.HeomObservable(kind, int(r0["observable"].get("ground", 0)),
                                                    mu.ctypes.data_as(dp)),
-                               1 if hermitian else 0)
+                               1 if hermitian else 0, int(form))
         t = ctypes.c_uint64()
         check(load().heom_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
         self._keep[t.value] = len(runs)
@@ -358,7 +359,7 @@ class Server:
     def _result(self, ticket, res, status):
         n_runs = self._keep.get(ticket, 1)
         out = {"status": status, "t_submit": res.t_submit_s, "t_admit": res.t_admit_s,
-               "t_finish": res.t_finish_s, "records": None}
+               "t_finish": res.t_finish_s, "form": res.form, "records": None}
         if status == _abi.HEOM_OK and res.records:
             n = n_runs * res.n_records * res.record_doubles
             arr = np.ctypeslib.as_array(res.records, shape=(n,)).copy()

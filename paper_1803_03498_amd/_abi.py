@@ -56,7 +56,7 @@ class HeomRequest(ctypes.Structure):
     _fields_ = [("problem", HeomProblem), ("n_runs", ctypes.c_int32),
                 ("record_every", ctypes.c_int32), ("n_steps", ctypes.c_int64),
                 ("dt_fs", ctypes.c_double), ("rho0", ctypes.POINTER(ctypes.c_double)),
-                ("obs", HeomObservable), ("hermitian", ctypes.c_int32)]
+                ("obs", HeomObservable), ("hermitian", ctypes.c_int32), ("form", ctypes.c_int32)]
 
 
 class HeomResult(ctypes.Structure):
@@ -64,7 +64,8 @@ class HeomResult(ctypes.Structure):
                 ("record_doubles", ctypes.c_int32),
                 ("records", ctypes.POINTER(ctypes.c_double)),
                 ("t_submit_s", ctypes.c_double), ("t_admit_s", ctypes.c_double),
-                ("t_finish_s", ctypes.c_double)]
+                ("t_finish_s", ctypes.c_double),
+                ("form", ctypes.c_int32)]
 
 
 P = ctypes.POINTER

@@ -677,6 +677,13 @@ heom_status problem_rate_bound(const heom_problem* p, double* rate) {
     return s;
 }
 
+bool block_step_ok(const heom_problem* p, double dt) {
+    Derived d;
+    if (derive(p, d) != HEOM_OK) return false;
+    const double shift = std::fabs(d.h_shift);
+    return dt * (d.rate_bound + shift) <= kRk4RealLimit && dt * shift <= kBlockPhaseLimit;
+}
+
 double rk4_real_limit() { return kRk4RealLimit; }
 
 void set_last_error(const std::string& msg) { g_error = msg; }

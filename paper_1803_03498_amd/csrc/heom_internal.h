@@ -99,6 +99,19 @@ struct StageSpec {
     int32_t mirror_in, mirror_out;
 };
 
+// One coherence-block request in a batched launch (device job table).
+struct BlockJob {
+    Tables t;
+    void* y[4];           // complex128 [n_ado][N][3]: the state (0) and stage copies
+    double dt;
+    int64_t elem_begin;   // first element of this job in the launch
+    const double* obs;    // [3][N] observed vectors
+    double* rec;          // [n_rec][6]
+    int32_t* status;      // set to 1 by a non-finite record
+    int64_t* step;        // steps completed, advanced by the record kernel
+    int32_t record_every;
+};
+
 // Kernel launchers (heom_kernels.hip).  All enqueue on `stream` and return the
 // HIP error of the launch.
 hipError_t launch_enumerate(const Tables& t, hipStream_t stream);
@@ -113,6 +126,13 @@ hipError_t launch_block_stage(const Tables& t, const void* in, void* out, const 
 // a non-finite value sets *status = 1.
 hipError_t launch_block_record(const void* y, const double* obs, int N, double* rec,
                                int32_t* status, hipStream_t stream);
+// The same stage over many requests of a device job table; total = the
+// last job's elem_begin plus its n_ado * 3 * N.
+hipError_t launch_block_stage_batched(const BlockJob* jobs_dev, int n_jobs, int64_t total,
+                                      const StageSpec& sp, hipStream_t stream);
+// After each step: every job's step counter advances; jobs whose record is
+// due write P into rec + 6 * (step / record_every).
+hipError_t launch_block_record_batched(const BlockJob* jobs_dev, int n_jobs, hipStream_t stream);
 // Fluorescence start: Y_u = sigma_u mu^+ embedded in the (N+1)-state ADOs
 // (precisions 0 = complex128, 1 = complex64 for the bulk of each side).
 hipError_t launch_emission_start(const void* in_sig0, const void* in_rest, int in_prec,
@@ -171,6 +191,9 @@ size_t control_bytes(int N);
 Job bind_workspace(const heom_hierarchy* h, heom_state io, char* work, double dt,
                    int64_t n_steps, int record_every, int kind, int ground, int hermitian);
 heom_status problem_rate_bound(const heom_problem* p, double* rate);
+// The step check of heom_propagate_block (rate bound plus the kept diagonal
+// offset, and the offset's phase per step) for the excited-state problem p.
+bool block_step_ok(const heom_problem* p, double dt);
 double rk4_real_limit();
 void set_last_error(const std::string& msg);
 void rk4_stage_specs(StageSpec sp[4]);           // the four classic RK4 stages

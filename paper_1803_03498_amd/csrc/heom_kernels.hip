@@ -1623,11 +1623,11 @@ struct BlockBases {
     double w[3];
 };
 
-__global__ __launch_bounds__(256) void k_block_stage(Tables t, const void* in, void* out,
-                                                     BlockBases bb, int nbase, double w_in,
-                                                     double h, int64_t total) {
-    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= total) return;
+// One element idx = (u * N + a) * 3 + p of a stage; shared by the
+// single-request and the batched kernels so both round the same way.
+__device__ __forceinline__ void block_stage_elem(const Tables& t, const void* in, void* out,
+                                                 const BlockBases& bb, int nbase, double w_in,
+                                                 double h, int64_t idx) {
     const int N = t.N, W = t.W, D = t.D, Dm = D > 0 ? D : 1, R = 3 * N;
     const int64_t u = idx / R;
     const int r = (int)(idx - u * R), a = r / 3, p = r - (r / 3) * 3;
@@ -1638,12 +1638,12 @@ __global__ __launch_bounds__(256) void k_block_stage(Tables t, const void* in, v
     for (int b = 0; b < N; ++b) {
         const double hr = G(t.h_re)[a * N + b], hi = t.h_complex ? G(t.h_im)[a * N + b] : 0.0;
         const cpx<double> y = Y(u, b);
-        cr += hr * y.re - hi * y.im;
-        ci += hr * y.im + hi * y.re;
+        cr = fma(hr, y.re, fma(-hi, y.im, cr));
+        ci = fma(hr, y.im, fma(hi, y.re, ci));
     }
     const cpx<double> y0 = Y(u, a);
     const double g = G(t.damping)[u] + G(t.delta_state)[a];
-    double fr = ci - g * y0.re, fi = -cr - g * y0.im;
+    double fr = fma(-g, y0.re, ci), fi = fma(-g, y0.im, -cr);
     if (G(t.level)[u] < D) {
         for (int m = G(t.state_mode_begin)[a]; m < G(t.state_mode_begin)[a + 1]; ++m) {
             const int l = G(t.state_modes)[m];
@@ -1651,8 +1651,8 @@ __global__ __launch_bounds__(256) void k_block_stage(Tables t, const void* in, v
             if (nb < 0) continue;
             const double w = G(t.plus_w)[(size_t)u * W + l];
             const cpx<double> x = Y(nb, a);
-            fr -= w * x.im;
-            fi += w * x.re;
+            fr = fma(-w, x.im, fr);
+            fi = fma(w, x.re, fi);
         }
     }
     for (int k = 0; k < Dm; ++k) {
@@ -1662,35 +1662,88 @@ __global__ __launch_bounds__(256) void k_block_stage(Tables t, const void* in, v
         if (nb < 0) continue;
         const pair_d w = G(reinterpret_cast<const pair_d*>(t.mlist_w))[at];
         const cpx<double> x = Y(nb, a);
-        fr += w.x * x.re - w.y * x.im;
-        fi += w.x * x.im + w.y * x.re;
+        fr = fma(w.x, x.re, fma(-w.y, x.im, fr));
+        fi = fma(w.x, x.im, fma(w.y, x.re, fi));
     }
-    double yr = w_in * y0.re + h * fr, yi = w_in * y0.im + h * fi;
+    double yr = fma(h, fr, w_in * y0.re), yi = fma(h, fi, w_in * y0.im);
     for (int m = 0; m < nbase; ++m) {
         const cpx<double> b = ld<double>(bb.p[m], (size_t)idx);
-        yr += bb.w[m] * b.re;
-        yi += bb.w[m] * b.im;
+        yr = fma(bb.w[m], b.re, yr);
+        yi = fma(bb.w[m], b.im, yi);
     }
     st<double>(out, (size_t)idx, cpx<double>{yr, yi});
+}
+
+__global__ __launch_bounds__(256) void k_block_stage(Tables t, const void* in, void* out,
+                                                     BlockBases bb, int nbase, double w_in,
+                                                     double h, int64_t total) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    block_stage_elem(t, in, out, bb, nbase, w_in, h, idx);
+}
+
+// Many coherence-block requests in one launch: job j owns the elements
+// [elem_begin, elem_begin + n_ado * 3 * N) of the launch.
+__global__ __launch_bounds__(256) void k_block_stage_batched(const BlockJob* jobs, int n_jobs,
+                                                             StageSpec sp, int64_t total) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (G(&jobs[mid].elem_begin)[0] <= idx) lo = mid;
+        else hi = mid - 1;
+    }
+    const BlockJob& J = jobs[lo];
+    BlockBases bb{};
+    for (int m = 0; m < sp.nbase; ++m) {
+        bb.p[m] = J.y[sp.base[m]];
+        bb.w[m] = sp.wbase[m];
+    }
+    block_stage_elem(J.t, J.y[sp.in], J.y[sp.out], bb, sp.nbase, sp.w_in, sp.hmul * J.dt,
+                     idx - J.elem_begin);
 }
 
 struct ObsArg {
     double v[3][64];
 };
 
-__global__ __launch_bounds__(64) void k_block_record(const void* y, ObsArg obs, int N, double* rec,
-                                                     int32_t* status) {
-    const int p = threadIdx.x;
-    if (p >= 3) return;
+// P_p = sum_a obs[p][a] Y_0[a][p], written as (Re, Im) pairs at rec[2p].
+template <class Obs>
+__device__ __forceinline__ void block_project(const void* y, const Obs& obs, int N, int p,
+                                              double* rec, int32_t* status) {
     double pr = 0.0, pi = 0.0;
     for (int a = 0; a < N; ++a) {
         const cpx<double> x = ld<double>(y, (size_t)a * 3 + p);
-        pr += obs.v[p][a] * x.re;
-        pi += obs.v[p][a] * x.im;
+        const double o = obs(p, a);
+        pr = fma(o, x.re, pr);
+        pi = fma(o, x.im, pi);
     }
     G(rec)[2 * p] = pr;
     G(rec)[2 * p + 1] = pi;
     if (!(isfinite(pr) && isfinite(pi))) *G(status) = 1;
+}
+
+__global__ __launch_bounds__(64) void k_block_record(const void* y, ObsArg obs, int N, double* rec,
+                                                     int32_t* status) {
+    const int p = threadIdx.x;
+    if (p >= 3) return;
+    block_project(y, [&](int q, int a) { return obs.v[q][a]; }, N, p, rec, status);
+}
+
+// One workgroup per job: advance the job's step counter and, when the
+// record is due, write it.
+__global__ __launch_bounds__(64) void k_block_record_batched(const BlockJob* jobs) {
+    const BlockJob& J = jobs[blockIdx.x];
+    const int64_t s = G(J.step)[0] + 1;
+    __syncthreads();
+    if (threadIdx.x == 0) G(J.step)[0] = s;
+    const int p = threadIdx.x;
+    if (p >= 3 || s % J.record_every != 0) return;
+    const double* o = J.obs;
+    const int N = J.t.N;
+    block_project(J.y[0], [&](int q, int a) { return G(o)[q * N + a]; }, N, p,
+                  J.rec + 6 * (s / J.record_every), J.status);
 }
 
 // Fluorescence start (section "Static Fluorescence Spectra": the dipole
@@ -1775,6 +1828,21 @@ hipError_t launch_block_record(const void* y, const double* obs, int N, double* 
     for (int p = 0; p < 3; ++p)
         for (int a = 0; a < N; ++a) o.v[p][a] = obs[p * N + a];
     hipLaunchKernelGGL(k_block_record, dim3(1), dim3(64), 0, stream, y, o, N, rec, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_stage_batched(const BlockJob* jobs_dev, int n_jobs, int64_t total,
+                                      const StageSpec& sp, hipStream_t stream) {
+    if (n_jobs < 1 || total <= 0) return hipSuccess;
+    if (sp.nbase < 0 || sp.nbase > 3) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_block_stage_batched, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                       stream, jobs_dev, n_jobs, sp, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_record_batched(const BlockJob* jobs_dev, int n_jobs, hipStream_t stream) {
+    if (n_jobs < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_block_record_batched, dim3((unsigned)n_jobs), dim3(64), 0, stream, jobs_dev);
     return hipGetLastError();
 }
 

@@ -12,6 +12,16 @@
 // are copied to pinned host memory and their arena ranges are freed once the
 // copy has completed on the stream.
 //
+// Two kinds of request leave the batched launches.  A large FP32 population
+// run with 10 <= N <= 64 gets launches of its own on the persistent
+// matrix-core kernel (its ADOs fill the device).  An eligible dipole request
+// (ground state uncoupled, initial states in the (e, g) column, at most three
+// directions) runs in the coherence-block form of heom_propagate_block: its
+// ADOs keep only their (e, g) column, the three directions side by side
+// (section "Linear absorption spectra"), 3N instead of 3 (N+1)^2 elements.
+// Both choices depend on the request alone, so results stay the same alone
+// and in the mix.
+//
 // Independent propagations (disorder realisations, dipole directions) are the
 // parallelism the paper runs side by side for rotational averages and
 // polarisation sequences (section "Distributed memory HEOM implementation").
@@ -37,6 +47,8 @@ namespace {
 constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 constexpr int kMaxRuns = 8;
 constexpr size_t kPinnedPool = size_t(256) << 20;
+// Population runs at least this large get launches of their own.
+constexpr int64_t kSoloMinAdos = 2048;
 
 // First-fit allocator of 256-byte-aligned ranges of [0, size).
 class RangeAllocator {
@@ -102,10 +114,42 @@ struct Req {
     heom_status status = HEOM_PENDING;
     std::vector<double> records;
     double t_submit = 0.0, t_admit = 0.0, t_finish = 0.0;
+    // coherence-block form: the excited-state problem (ground energy 0),
+    // observables [3][bN], start column [bN][3] complex, and the device block
+    // state, its three stage copies, records [n_rec][6] and status word
+    bool block = false;
+    int bN = 0;
+    std::vector<double> bh_re, bh_im, bobs, bstart;
+    std::vector<heom_bath> bbaths;
+    heom_problem bprob{};
+    heom_info binfo{};
+    size_t bstate_bytes = 0, bwork_bytes = 0;
+    void* barr[4] = {nullptr, nullptr, nullptr, nullptr};
+    double* brec = nullptr;
+    double* bobs_dev = nullptr;
+    int32_t* bstatus = nullptr;
+    int64_t* bstep = nullptr;
+    // pinned layout of a block request: start column | obs | records | status
+    size_t bpin_obs() const { return align256((size_t)bN * 3 * 16); }
+    size_t bpin_rec() const { return bpin_obs() + align256((size_t)3 * bN * 8); }
+    size_t bpin_status() const { return bpin_rec() + align256((size_t)n_rec * 6 * 8); }
 };
+
+// Device bytes of the job tables at the start of the arena: full-form jobs
+// (up to kMaxRuns per request), then one coherence-block job per request.
+size_t job_table_bytes(size_t jobs_cap, int max_active) {
+    return align256(jobs_cap * sizeof(heom::Job)) + align256((size_t)max_active * sizeof(heom::BlockJob));
+}
+
+// A full-form job with launches of its own (persistent kernel).
+bool solo_job(int precision, const heom::Job& j) {
+    return precision == HEOM_FP32_MIXED && j.herm && j.t.N >= 10 && j.t.N <= 64 &&
+           j.t.h_complex == 0 && j.t.n_ado >= kSoloMinAdos;
+}
 
 struct Group {
     int precision = 0, nb = 0, herm = 0;
+    bool solo = false;  // one job, launched on its own
     int job_off = 0, n_jobs = 0, tiles = 0;
     heom::Job sizing{};
 };
@@ -123,6 +167,10 @@ struct heom_server {
     heom::Job* jobs_dev = nullptr;    // in the arena
     heom::Job* jobs_stage = nullptr;  // pinned staging for the job table
     size_t jobs_cap = 0;
+    heom::BlockJob* bjobs_dev = nullptr;    // after the job table
+    heom::BlockJob* bjobs_stage = nullptr;  // after its staging
+    int n_bjobs = 0;
+    int64_t btotal = 0;  // elements of one batched block stage
     hipEvent_t stage_ev = nullptr;
     hipEvent_t step_ev[2] = {nullptr, nullptr};
     int64_t macro = 0;
@@ -211,12 +259,46 @@ void heom_server::fail_all_locked(const char* what, hipError_t e) {
 }
 
 // Device and pinned layout of one request (offsets from its ranges):
-//   arena: tables | per run: sigma0, rest, workspace
-//   pinned: per run: rho0, control block, records, status
+//   full form   arena: tables | per run: sigma0, rest, workspace
+//               pinned: per run: rho0, control block, records, status
+//   block form  arena: tables | state | work | observed vectors
+//               pinned: start column | observed vectors | records | status
 bool heom_server::setup(Req* r) {
     char* base = arena + r->arena_off;
     char* pin = pinned + r->pinned_off;
     hipError_t e;
+    if (r->block) {
+        // arena: tables | block state | status, three stage copies, records
+        heom_status s = heom_build_hierarchy(&r->bprob, base, r->binfo.tables_bytes, stream, &r->h);
+        if (s != HEOM_OK) {
+            std::lock_guard<std::mutex> lk(mu);
+            finish(r, s);
+            return false;
+        }
+        // arena: tables | state | work (status, step counter; three stage
+        // copies; records) | observed vectors
+        char* st = base + align256(r->binfo.tables_bytes);
+        char* w = st + r->bstate_bytes;
+        const size_t copy = align256((size_t)r->binfo.n_ado * r->bN * 3 * 16);
+        r->barr[0] = st;
+        for (int k = 1; k < 4; ++k) r->barr[k] = w + 256 + (size_t)(k - 1) * copy;
+        r->bstatus = reinterpret_cast<int32_t*>(w);
+        r->bstep = reinterpret_cast<int64_t*>(w + 8);
+        r->brec = reinterpret_cast<double*>(w + 256 + 3 * copy);
+        r->bobs_dev = reinterpret_cast<double*>(w + r->bwork_bytes);
+        const size_t col = (size_t)r->bN * 3 * 16, ob = (size_t)3 * r->bN * 8;
+        std::memcpy(pin, r->bstart.data(), col);
+        std::memcpy(pin + r->bpin_obs(), r->bobs.data(), ob);
+        if ((e = hipMemsetAsync(st, 0, r->bstate_bytes, stream)) ||
+            (e = hipMemsetAsync(w, 0, 256, stream)) ||
+            (e = hipMemcpyAsync(st, pin, col, hipMemcpyHostToDevice, stream)) ||
+            (e = hipMemcpyAsync(r->bobs_dev, pin + r->bpin_obs(), ob, hipMemcpyHostToDevice, stream)) ||
+            (e = heom::launch_block_record(st, r->bobs.data(), r->bN, r->brec, r->bstatus, stream))) {
+            fail_all("request setup", e);
+            return false;
+        }
+        return true;
+    }
     heom_status s = heom_build_hierarchy(&r->prob, base, r->info.tables_bytes, stream, &r->h);
     if (s != HEOM_OK) {
         std::lock_guard<std::mutex> lk(mu);
@@ -297,12 +379,17 @@ void heom_server::admit() {
 
 bool heom_server::rebuild() {
     groups.clear();
-    std::map<std::tuple<int, int, int>, std::vector<const heom::Job*>> by_key;
+    // key: precision, MFMA blocks, Hermitian path, and -1 for batched jobs
+    // or the index of a job launched on its own
+    std::map<std::tuple<int, int, int, int>, std::vector<const heom::Job*>> by_key;
+    int n_solo = 0;
     for (Req* r : active) {
+        if (r->block) continue;
         const int prec = heom::hierarchy_precision(r->h);
         for (const heom::Job& j : r->jobs) {
             const int nb = heom::bulk_mfma_blocks(j.t.N, j.t.h_complex != 0, prec);
-            by_key[std::make_tuple(prec, nb, nb ? j.herm : 0)].push_back(&j);
+            const int solo = solo_job(prec, j) ? n_solo++ : -1;
+            by_key[std::make_tuple(prec, nb, nb ? j.herm : 0, solo)].push_back(&j);
         }
     }
     size_t n = 0;
@@ -312,12 +399,30 @@ bool heom_server::rebuild() {
         return false;
     }
     if (stage_ev) (void)hipEventSynchronize(stage_ev);  // staging buffer free again
+    n_bjobs = 0;
+    btotal = 0;
+    for (Req* r : active) {
+        if (!r->block) continue;
+        heom::BlockJob& b = bjobs_stage[n_bjobs++];
+        b = heom::BlockJob{};
+        b.t = heom::hierarchy_tables(r->h);
+        for (int k = 0; k < 4; ++k) b.y[k] = r->barr[k];
+        b.dt = r->dt;
+        b.elem_begin = btotal;
+        b.obs = r->bobs_dev;
+        b.rec = r->brec;
+        b.status = r->bstatus;
+        b.step = r->bstep;
+        b.record_every = r->record_every;
+        btotal += (int64_t)r->binfo.n_ado * 3 * r->bN;
+    }
     int off = 0;
     for (auto& kv : by_key) {
         Group g;
         g.precision = std::get<0>(kv.first);
         g.nb = std::get<1>(kv.first);
         g.herm = std::get<2>(kv.first);
+        g.solo = std::get<3>(kv.first) >= 0;
         g.job_off = off;
         g.n_jobs = (int)kv.second.size();
         g.sizing = *kv.second.front();
@@ -345,10 +450,17 @@ bool heom_server::rebuild() {
         g.sizing.lds_bytes = (uint32_t)fma_bytes;
         g.sizing.any_complex_h = any_hc;
         if (g.nb == 0) g.sizing.t.h_complex = 1;  // selects the FMA path for any N
+        if (g.solo) {
+            g.sizing = *kv.second.front();  // the job itself, launched alone
+            g.tiles = g.sizing.t.n_ado > 1 ? g.sizing.n_tiles : 0;
+        }
         groups.push_back(g);
     }
     hipError_t e = hipMemcpyAsync(jobs_dev, jobs_stage, n * sizeof(heom::Job),
                                   hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && n_bjobs)
+        e = hipMemcpyAsync(bjobs_dev, bjobs_stage, n_bjobs * sizeof(heom::BlockJob),
+                           hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipEventRecord(stage_ev, stream);
     if (e != hipSuccess) {
         fail_all("job table upload", e);
@@ -363,12 +475,16 @@ bool heom_server::launch_macro_step() {
     heom::rk4_stage_specs(sp);
     hipError_t e = hipSuccess;
     if (macro >= 2) e = hipEventSynchronize(step_ev[macro % 2]);  // at most two steps in flight
-    for (int k = 0; k < 4 && e == hipSuccess; ++k)
+    for (int k = 0; k < 4 && e == hipSuccess; ++k) {
         for (const Group& g : groups) {
-            e = heom::launch_stage(g.sizing, jobs_dev + g.job_off, g.n_jobs, g.tiles, g.precision,
-                                   sp[k], stream);
+            e = heom::launch_stage(g.sizing, g.solo ? nullptr : jobs_dev + g.job_off,
+                                   g.solo ? 0 : g.n_jobs, g.tiles, g.precision, sp[k], stream);
             if (e != hipSuccess) break;
         }
+        // every coherence-block request in one launch per stage
+        if (e == hipSuccess) e = heom::launch_block_stage_batched(bjobs_dev, n_bjobs, btotal, sp[k], stream);
+    }
+    if (e == hipSuccess) e = heom::launch_block_record_batched(bjobs_dev, n_bjobs, stream);
     if (e == hipSuccess) e = hipEventRecord(step_ev[macro % 2], stream);
     if (e != hipSuccess) {
         fail_all("macro-step launch", e);
@@ -384,7 +500,13 @@ void heom_server::start_drain(Req* r) {
     const size_t NN = (size_t)N * N;
     size_t poff = 0;
     hipError_t e = hipSuccess;
-    for (int k = 0; k < r->n_runs && e == hipSuccess; ++k) {
+    if (r->block) {
+        e = hipMemcpyAsync(pin + r->bpin_rec(), r->brec, (size_t)r->n_rec * 6 * 8,
+                           hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(pin + r->bpin_status(), r->bstatus, 4, hipMemcpyDeviceToHost, stream);
+    }
+    for (int k = 0; !r->block && k < r->n_runs && e == hipSuccess; ++k) {
         poff += align256(NN * 16) + align256(heom::control_bytes(N));
         const heom::Job& j = r->jobs[k];
         const size_t rec_bytes = (size_t)r->n_rec * r->rd * 8;
@@ -420,7 +542,18 @@ void heom_server::finish_draining() {
         r->records.assign(rec_doubles * r->n_runs, 0.0);
         size_t poff = 0;
         int32_t bad = 0;
-        for (int k = 0; k < r->n_runs; ++k) {
+        if (r->block) {
+            // the full form's dipole records [Re P, Im P, Re Tr, Im Tr]; the
+            // (e, g) block has no diagonal element, so the trace is 0
+            const double* rec6 = reinterpret_cast<const double*>(pin + r->bpin_rec());
+            for (int k = 0; k < r->n_runs; ++k)
+                for (int64_t q = 0; q < r->n_rec; ++q) {
+                    r->records[rec_doubles * k + q * r->rd] = rec6[6 * q + 2 * k];
+                    r->records[rec_doubles * k + q * r->rd + 1] = rec6[6 * q + 2 * k + 1];
+                }
+            std::memcpy(&bad, pin + r->bpin_status(), 4);
+        }
+        for (int k = 0; !r->block && k < r->n_runs; ++k) {
             poff += align256(NN * 16) + align256(heom::control_bytes(N));
             std::memcpy(r->records.data() + rec_doubles * k, pin + poff, rec_doubles * 8);
             poff += align256(rec_doubles * 8);
@@ -497,12 +630,13 @@ heom_status heom_server_create(void* arena_dev, size_t arena_bytes, int32_t max_
     s->max_active = max_active;
     s->stream = static_cast<hipStream_t>(stream);
     s->jobs_cap = (size_t)max_active * kMaxRuns;
-    const size_t table_bytes = align256(s->jobs_cap * sizeof(heom::Job));
+    const size_t table_bytes = job_table_bytes(s->jobs_cap, max_active);
     if (arena_bytes <= table_bytes) {
         delete s;
         return srv_fail(HEOM_E_NOMEM, "arena smaller than the job table");
     }
     s->jobs_dev = reinterpret_cast<heom::Job*>(s->arena);
+    s->bjobs_dev = reinterpret_cast<heom::BlockJob*>(s->arena + align256(s->jobs_cap * sizeof(heom::Job)));
     s->arena_bytes = arena_bytes;
     // the job table occupies the start of the arena
     s->arena_alloc.reset(arena_bytes);
@@ -512,6 +646,9 @@ heom_status heom_server_create(void* arena_dev, size_t arena_bytes, int32_t max_
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->pinned), kPinnedPool, 0);
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&s->jobs_stage), table_bytes, 0);
+    if (e == hipSuccess)
+        s->bjobs_stage = reinterpret_cast<heom::BlockJob*>(reinterpret_cast<char*>(s->jobs_stage) +
+                                                            align256(s->jobs_cap * sizeof(heom::Job)));
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->stage_ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->step_ev[0], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->step_ev[1], hipEventDisableTiming);
@@ -525,6 +662,32 @@ heom_status heom_server_create(void* arena_dev, size_t arena_bytes, int32_t max_
     s->thr = std::thread([s] { s->run(); });
     *out = s;
     return HEOM_OK;
+}
+
+// A dipole request the coherence-block form can run: at most three
+// directions, the ground state without a bath and without coupling, and
+// initial states zero outside column g (rows != g).  The block step check
+// comes after, on the block problem.
+static bool block_eligible(const heom_request& q, int N) {
+    if (q.obs.kind != HEOM_OBS_DIPOLE || q.n_runs > 3 || N < 2 || N - 1 > 64) return false;
+    const int g = q.obs.ground;
+    const double* H = q.problem.h_re_cm;
+    for (int a = 0; a < N; ++a)
+        if (a != g && (H[(size_t)a * N + g] != 0.0 || H[(size_t)g * N + a] != 0.0)) return false;
+    if (q.problem.h_im_cm)
+        for (size_t e = 0; e < (size_t)N * N; ++e)
+            if (q.problem.h_im_cm[e] != 0.0) return false;
+    for (int b = 0; b < q.problem.n_baths; ++b)
+        if (q.problem.baths[b].state == g) return false;
+    const size_t NN = (size_t)N * N;
+    for (int k = 0; k < q.n_runs; ++k)
+        for (int a = 0; a < N; ++a)
+            for (int b = 0; b < N; ++b) {
+                if (b == g && a != g) continue;
+                const double* z = q.rho0 + 2 * (NN * k + (size_t)a * N + b);
+                if (z[0] != 0.0 || z[1] != 0.0) return false;
+            }
+    return true;
 }
 
 heom_status heom_submit(heom_server* s, const heom_request* q, uint64_t* ticket) {
@@ -575,7 +738,55 @@ heom_status heom_submit(heom_server* s, const heom_request* q, uint64_t* ticket)
     r->footprint = align256(info.tables_bytes) + (size_t)q->n_runs * (r->state_bytes + r->work_bytes);
     r->pinned_bytes = (size_t)q->n_runs * (align256(NN * 16) + align256(heom::control_bytes(N)) +
                                            align256((size_t)r->n_rec * r->rd * 8) + 256);
-    const size_t usable = s->arena_bytes - align256(s->jobs_cap * sizeof(heom::Job));
+    if (q->form != HEOM_FORM_AUTO && q->form != HEOM_FORM_FULL)
+        return srv_fail(HEOM_E_INVAL, "form unknown");
+    if (q->form == HEOM_FORM_AUTO && block_eligible(*q, N)) {
+        // the excited block (rows and columns != g) with the ground energy
+        // subtracted, the baths renumbered, and the (e, g) columns of the
+        // initial states as the start of the three directions
+        const int g = q->obs.ground, bN = N - 1;
+        r->bN = bN;
+        r->bh_re.resize((size_t)bN * bN);
+        for (int a = 0, i = 0; a < N; ++a) {
+            if (a == g) continue;
+            for (int b = 0, j = 0; b < N; ++b) {
+                if (b == g) continue;
+                r->bh_re[(size_t)i * bN + j] =
+                    q->problem.h_re_cm[(size_t)a * N + b] - (a == b ? q->problem.h_re_cm[(size_t)g * N + g] : 0.0);
+                ++j;
+            }
+            ++i;
+        }
+        r->bbaths = r->baths;
+        for (heom_bath& b : r->bbaths) b.state -= b.state > g ? 1 : 0;
+        r->bprob = r->prob;
+        r->bprob.n_states = bN;
+        r->bprob.h_re_cm = r->bh_re.data();
+        r->bprob.h_im_cm = nullptr;
+        r->bprob.baths = r->bbaths.data();
+        heom_info bi;
+        if (heom_plan(&r->bprob, &bi) == HEOM_OK && heom::block_step_ok(&r->bprob, q->dt_fs)) {
+            r->block = true;
+            r->binfo = bi;
+            r->bobs.assign((size_t)3 * bN, 0.0);
+            r->bstart.assign((size_t)bN * 3 * 2, 0.0);
+            for (int k = 0; k < q->n_runs; ++k)
+                for (int a = 0, i = 0; a < N; ++a) {
+                    if (a == g) continue;
+                    r->bobs[(size_t)k * bN + i] = q->obs.mu[(size_t)k * N + a];
+                    const double* z = q->rho0 + 2 * (NN * k + (size_t)a * N + g);
+                    r->bstart[2 * ((size_t)i * 3 + k)] = z[0];
+                    r->bstart[2 * ((size_t)i * 3 + k) + 1] = z[1];
+                    ++i;
+                }
+            r->bstate_bytes = align256((size_t)bi.n_ado * bN * 3 * 16);
+            r->bwork_bytes = align256(heom_block_work_bytes(&bi, q->n_steps, q->record_every));
+            r->footprint = align256(bi.tables_bytes) + r->bstate_bytes + r->bwork_bytes +
+                           align256((size_t)3 * bN * 8);
+            r->pinned_bytes = r->bpin_status() + 256;
+        }
+    }
+    const size_t usable = s->arena_bytes - job_table_bytes(s->jobs_cap, s->max_active);
     if (r->footprint > usable || r->pinned_bytes > kPinnedPool)
         return srv_fail(HEOM_E_NOMEM, "request can never fit the arena");
     r->t_submit = heom::monotonic_seconds();
@@ -598,6 +809,7 @@ static void fill_result(const Req* r, heom_result* out) {
     out->t_submit_s = r->t_submit;
     out->t_admit_s = r->t_admit;
     out->t_finish_s = r->t_finish;
+    out->form = r->block ? HEOM_FORM_BLOCK : HEOM_FORM_FULL;
 }
 
 heom_status heom_poll(heom_server* s, uint64_t ticket, heom_result* out) {

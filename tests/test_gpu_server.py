@@ -143,3 +143,123 @@ def test_cancel_and_queueing(heom):
     for t in tickets:
         srv.release(t)
     srv.close()
+
+
+# ------------------------------------------------ coherence-block requests ----
+
+def _absorption(seed, N, D, M, n_steps=60):
+    rng = np.random.default_rng(seed)
+    H = hi.fmo_like_hamiltonian(rng, N)
+    dip = hi.unit_vectors(rng, N)
+    baths = [{"state": s, "lambda_cm": 35.0, "tau_fs": 50.0, "matsubara": M} for s in range(N)]
+    return hi.absorption_runs(H, dip, baths, 300.0, D, 1.0, n_steps)
+
+
+def _block_problem(run):
+    return {"H": np.asarray(run["H"])[1:, 1:], "temperature_K": run["temperature_K"],
+            "depth": run["depth"], "flags": run.get("flags", 0),
+            "baths": [dict(b, state=b["state"] - 1) for b in run["baths"]]}
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_block_form_requests(heom, orc, precision):
+    # eligible absorption requests run in the coherence-block form (FP64 for
+    # either request precision): the same records as heom_propagate_block bit
+    # for bit, a zero trace, and the oracle's full-matrix correlations
+    for seed, N, D, M in [(21, 3, 3, 1), (22, 6, 2, 1), (23, 12, 3, 0)]:
+        _case("block request", precision, seed, N, D, M)
+        runs = _absorption(seed, N, D, M)
+        srv = heom.Server(ARENA, max_active=4)
+        tb = srv.submit(runs, precision)
+        tf = srv.submit(runs, precision, form=1)
+        rb, rf = srv.wait(tb, 120.0), srv.wait(tf, 120.0)
+        srv.close()
+        assert rb["status"] == 0 and rf["status"] == 0
+        assert rb["form"] == 2 and rf["form"] == 1
+        assert np.all(rb["records"][:, :, 2:] == 0.0)
+        P = rb["records"][:, :, 0] + 1j * rb["records"][:, :, 1]
+        mu3 = np.stack([r["observable"]["mu"][1:] for r in runs])
+        h = heom.Hierarchy(_block_problem(runs[0]), precision)
+        P_direct = h.propagate_block(h.block_state(mu3), 1.0, runs[0]["n_steps"], 1, mu3).T
+        assert np.array_equal(P, P_direct)
+        P_full = rf["records"][:, :, 0] + 1j * rf["records"][:, :, 1]
+        tol = 1e-12 if precision == 0 else 1e-5
+        assert np.max(np.abs(P - P_full)) <= tol * max(1.0, np.max(np.abs(P)))
+        if N <= 6:
+            recs = [orc.run(r)[1] for r in runs]
+            P_ref = np.stack([rec[:, 0] + 1j * rec[:, 1] for rec in recs])
+            assert np.max(np.abs(P - P_ref)) <= 1e-12 * max(1.0, np.max(np.abs(P_ref)))
+
+
+def test_block_form_eligibility(heom):
+    # requests the block form cannot run stay on full matrices, with the same
+    # correlations as heom_propagate
+    runs = _absorption(31, 4, 3, 1, n_steps=40)
+    bath_on_g = [dict(r, baths=r["baths"] + [{"state": 0, "lambda_cm": 20.0, "tau_fs": 80.0,
+                                              "matsubara": 0}]) for r in runs]
+    coupled = []
+    for r in runs:
+        H = np.array(r["H"])
+        H[0, 2] = H[2, 0] = 15.0
+        coupled.append(dict(r, H=H))
+    diag_g = []
+    for r in runs:
+        rho0 = np.array(r["rho0"])
+        rho0[0, 0] = 0.25
+        diag_g.append(dict(r, rho0=rho0))
+    unrotated = []
+    for r in runs:
+        H = np.array(r["H"])
+        H[1:, 1:] += 5000.0 * np.eye(4)  # 0.94 rad per 1-fs step
+        unrotated.append(dict(r, H=H))
+    four = runs + [runs[0]]
+    cases = [("eligible", runs, 2), ("bath on ground", bath_on_g, 1), ("ground coupled", coupled, 1),
+             ("ground population", diag_g, 1), ("unrotated frame", unrotated, 1),
+             ("four runs", four, 1)]
+    srv = heom.Server(ARENA, max_active=8)
+    tickets = [srv.submit(c, heom.FP64) for _, c, _ in cases]
+    for (name, c, form), t in zip(cases, tickets):
+        _case("eligibility", name)
+        res = srv.wait(t, 120.0)
+        assert res["status"] == 0, name
+        assert res["form"] == form, name
+        ref = _alone(heom, c, heom.FP64)
+        assert np.max(np.abs(res["records"] - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref))), name
+    srv.close()
+
+
+# ------------------------------------------ matrix-core groups in the mix ----
+
+def _population(seed, N, D, M, n_steps=20):
+    rng = np.random.default_rng(seed)
+    H = hi.fmo_like_hamiltonian(rng, N)
+    baths = [{"state": s, "lambda_cm": 35.0, "tau_fs": 50.0, "matsubara": M} for s in range(N)]
+    return [{"H": H, "baths": baths, "temperature_K": 300.0, "depth": D, "flags": 0,
+             "dt_fs": 1.0, "n_steps": n_steps, "record_every": 1,
+             "rho0": hi.population_rho0(N, N // 2), "observable": {"kind": "population"}}]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_matrix_core_sizes_in_the_mix(heom, precision):
+    # N = 16, 17, 24, 33 (one, two and three 16-row blocks, ragged) beside
+    # small FMA-path requests; in FP32 the 4845- and 7140-ADO runs get
+    # launches of their own.  Mix and alone agree bit for bit, and
+    # heom_propagate within the precision's tolerance.
+    specs = [(41, 16, 2, 0), (42, 17, 3, 0), (43, 24, 2, 0), (44, 33, 3, 0), (45, 16, 4, 0),
+             (46, 5, 3, 1), (47, 9, 2, 1), (48, 3, 4, 1)]
+    reqs = [_population(*s) for s in specs]
+    srv = heom.Server(ARENA, max_active=8)
+    tickets = [srv.submit(r, precision) for r in reqs]
+    results = [srv.wait(t, 120.0) for t in tickets]
+    srv.close()
+    tol = 1e-12 if precision == 0 else 1e-5
+    for s, r, res in zip(specs, reqs, results):
+        _case("matrix-core mix", precision, s)
+        assert res["status"] == 0
+        one = heom.Server(ARENA, max_active=1)
+        alone = one.wait(one.submit(r, precision), 120.0)
+        one.close()
+        assert np.array_equal(res["records"], alone["records"]), s
+        ref = _alone(heom, r, precision)
+        assert np.max(np.abs(res["records"] - ref)) <= tol, s
+        assert np.max(np.abs(ref[0, -1, :s[1]] - ref[0, 0, :s[1]])) > 1e-4  # populations moved
