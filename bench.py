@@ -104,11 +104,15 @@ def parse():
                     help="target CPU time of the oracle sample (0 disables it)")
     ap.add_argument("--no-fp64-check", action="store_true",
                     help="skip the untimed FP64 run of the same steps")
-    ap.add_argument("--serve-requests", type=int, default=128)
+    ap.add_argument("--serve-requests", type=int, default=512,
+                    help="requests in the serving mix (a prefix is run, see --serve-seconds)")
     ap.add_argument("--serve-steps", type=int, default=1000)
-    ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-seconds", type=float, default=150.0,
+                    help="time the serving replays may take (0 skips the serving leg)")
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-arena-gb", type=float, default=48.0)
+    ap.add_argument("--serve-log", default=None,
+                    help="write one JSON line per served request to this file")
     return ap.parse_args()
 
 
@@ -220,69 +224,156 @@ def _percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def _replay(heom, reqs, precision, max_active, arena_bytes, rate, timeout_s=600.0):
-    """Submit requests at their (scaled) Poisson arrival times; returns
-    latencies (s), makespan (s) and ADO-updates done."""
+def _replay(heom, reqs, precision, max_active, arena_bytes, rate, form=0, timeout_s=900.0,
+            log=None, tag=""):
+    """Submit requests at their (scaled) Poisson arrival times (all at once
+    when rate is None); returns per-request latencies (s), the makespan (s),
+    the ADO-updates done, the number of requests run in the coherence-block
+    form and each request's service time (finish - admission, s)."""
     srv = heom.Server(arena_bytes, max_active)
     t0 = time.monotonic()
     arrival = 0.0
     tickets = []
     for k, r in enumerate(reqs):
-        if rate is not None and (k + 1) % 16 == 0:
-            print("  submitted %d/%d, %.1f s" % (k + 1, len(reqs), time.monotonic() - t0),
-                  file=sys.stderr, flush=True)
         if rate is not None:
             arrival += r["gap"] / rate
             delay = t0 + arrival - time.monotonic()
             if delay > 0:
                 time.sleep(delay)
-        tickets.append(srv.submit(r["runs"], precision))
-    lat, work = [], 0
+        tickets.append(srv.submit(r["runs"], precision, form=form))
+    lat, work, n_block, service = [], 0, 0, []
     t_end = t0
     for k, (r, t) in enumerate(zip(reqs, tickets)):
         res = srv.wait(t, timeout_s)
-        if (k + 1) % 16 == 0 or k + 1 == len(reqs):
-            print("  %d/%d requests done, %.1f s" % (k + 1, len(reqs), time.monotonic() - t0),
-                  file=sys.stderr, flush=True)
         if res["status"] != 0:
             raise RuntimeError("request %d failed: %s" % (r["id"], res["status"]))
         lat.append(res["t_finish"] - res["t_submit"])
+        service.append(res["t_finish"] - res["t_admit"])
         t_end = max(t_end, res["t_finish"])
-        work += r["n_ado"] * r["runs"][0]["n_steps"] * len(r["runs"])
+        ado_updates = r["n_ado"] * r["runs"][0]["n_steps"] * len(r["runs"])
+        work += ado_updates
+        n_block += res["form"] == 2
+        if log is not None:
+            log.write(json.dumps({
+                "replay": tag, "request": r["id"], "kind": r["kind"], "N": r["N"],
+                "depth": r["depth"], "matsubara": r["matsubara"], "n_ado": r["n_ado"],
+                "runs": len(r["runs"]), "form": "block" if res["form"] == 2 else "full",
+                "queue_ms": 1e3 * (res["t_admit"] - res["t_submit"]),
+                "latency_ms": 1e3 * (res["t_finish"] - res["t_submit"]),
+                "ado_updates": ado_updates}) + "\n")
         srv.release(t)
     srv.close()
+    if log is not None:
+        log.flush()
     # t_finish is on the library's monotonic clock, like time.monotonic here
-    return lat, max(t_end - t0, 1e-9), work
+    return lat, max(t_end - t0, 1e-9), work, n_block, service
 
 
-def run_serve(args):
-    """Serving mix: continuous batching (FP32 bulk, FP64 sigma_0 and
-    reductions) against plain FP64 one-solve-at-a-time on the same GPU."""
+def _full_bytes(r):
+    """Bytes of one RK4 stage copy of a request on full matrices."""
+    return r["n_ado"] * r["N_full"] ** 2 * len(r["runs"])
+
+
+def _serve_stats(lat, span, work, n):
+    return {"p50_ms": 1e3 * _percentile(lat, 50), "p99_ms": 1e3 * _percentile(lat, 99),
+            "throughput_req_per_s": n / span, "ado_updates_per_s": work / span,
+            "makespan_s": span}
+
+
+def serve_leg(args):
+    """Serving mix (seed 512): continuous batching in FP32-mixed, with the
+    coherence-block form for absorption requests, against plain FP64
+    one-solve-at-a-time on full matrices, on the same Poisson traces at
+    0.5x, 0.8x and 1.0x of the batched server's closed-loop capacity.  The
+    longest prefix of the mix whose replays fit --serve-seconds is run."""
     import torch
 
     import paper_1803_03498_amd as heom
     torch.cuda.set_device(0)
-    reqs = hi.serving_mix(n_requests=args.serve_requests, seed=512, n_steps=args.serve_steps)
-    for r in reqs:
+    mix = hi.serving_mix(n_requests=args.serve_requests, seed=512, n_steps=args.serve_steps)
+    for r in mix:
         r["n_ado"] = heom.plan(r["runs"][0])["n_ado"]
+        r["N_full"] = np.asarray(r["runs"][0]["H"]).shape[0]
     arena = int(args.serve_arena_gb * (1 << 30))
-    # warm-up: kernels compiled/loaded, allocator primed
-    _replay(heom, reqs[:4], heom.FP32_MIXED, 8, arena, None)
+    slots = args.serve_slots
+    loads = (0.5, 0.8, 1.0)
+    log = open(args.serve_log, "w") if args.serve_log else None
+    print("serve: warm-up and pilot", file=sys.stderr, flush=True)
+    _replay(heom, mix[:4], heom.FP32_MIXED, 8, arena, None)
+    _replay(heom, mix[:2], heom.FP64, 1, arena, None, form=1)
     torch.cuda.synchronize()
-    # 1. closed-loop capacity of the batched server
-    lat_c, span_c, work_c = _replay(heom, reqs, heom.FP32_MIXED, args.serve_slots, arena, None)
-    capacity = len(reqs) / span_c
-    rate = args.serve_load * capacity
-    print("serve: %d requests, capacity %.2f req/s (%.1f s closed loop), replay at %.2f req/s"
-          % (len(reqs), capacity, span_c, rate), file=sys.stderr, flush=True)
-    # 2. the same Poisson trace through the batched server and through FP64 one-at-a-time
-    print("serve: batched FP32-mixed replay", file=sys.stderr, flush=True)
-    lat_b, span_b, work_b = _replay(heom, reqs, heom.FP32_MIXED, args.serve_slots, arena, rate)
-    print("serve: plain FP64 one-at-a-time replay", file=sys.stderr, flush=True)
-    lat_f, span_f, work_f = _replay(heom, reqs, heom.FP64, 1, arena, rate)
+    # pilot on the first requests (closed loop): the batched server's time per
+    # full-matrix byte, and plain FP64 service times fitted as a + b * bytes
+    n_pilot = min(32, len(mix))
+    pilot = mix[:n_pilot]
+    _, span_pb, _, _, _ = _replay(heom, pilot, heom.FP32_MIXED, slots, arena, None)
+    _, _, _, _, svc = _replay(heom, pilot[:16], heom.FP64, 1, arena, None, form=1)
+    x = np.array([_full_bytes(r) for r in pilot[:16]], float)
+    A = np.stack([np.ones_like(x), x], 1)
+    a, b = np.linalg.lstsq(A, np.array(svc), rcond=None)[0]
+    a, b = max(a, 0.0), max(b, 0.0)
+    b_per_byte = span_pb / sum(_full_bytes(r) for r in pilot)
+
+    def estimate(k):
+        wb = sum(_full_bytes(r) for r in mix[:k])
+        tb, tf = b_per_byte * wb, a * k + b * wb
+        # closed loop + three batched replays + three plain FP64 replays (each
+        # service-bound once the arrivals outpace plain FP64)
+        return tb * (1.0 + sum(1.0 / y for y in loads)) + sum(max(tf, tb / y) for y in loads)
+
+    n = len(mix)
+    while n > 16 and estimate(n) > args.serve_seconds:
+        n -= 8
+    reqs = mix[:n]
+    print("serve: pilot: batched %.3g s per 1e9 elements, plain FP64 %.3f s + %.3g s per 1e9 elements per request: %d of "
+          "%d requests, estimated %.0f s" % (b_per_byte * 1e9, a, b * 1e9, n, len(mix),
+                                             estimate(n)), file=sys.stderr, flush=True)
+    lat_c, span_c, work_c, n_block, _ = _replay(heom, reqs, heom.FP32_MIXED, slots, arena, None,
+                                                log=log, tag="closed_loop")
+    capacity = n / span_c
+    out = {
+        "requests": n, "requests_in_mix": len(mix),
+        "requests_block_form": n_block,
+        "steps_per_request": args.serve_steps, "slots": slots, "arena_GB": args.serve_arena_gb,
+        "capacity_req_per_s": capacity,
+        "closed_loop": _serve_stats(lat_c, span_c, work_c, n),
+        "replays": [],
+    }
+    for x in loads:
+        rate = x * capacity
+        print("serve: replay at %.1fx capacity (%.2f req/s): batched" % (x, rate),
+              file=sys.stderr, flush=True)
+        lat_b, span_b, work_b, _, _ = _replay(heom, reqs, heom.FP32_MIXED, slots, arena, rate,
+                                              log=log, tag="batched_%.1fx" % x)
+        print("serve: replay at %.1fx capacity: plain FP64" % x, file=sys.stderr, flush=True)
+        lat_f, span_f, work_f, _, _ = _replay(heom, reqs, heom.FP64, 1, arena, rate, form=1,
+                                              log=log, tag="plain_fp64_%.1fx" % x)
+        b, f = _serve_stats(lat_b, span_b, work_b, n), _serve_stats(lat_f, span_f, work_f, n)
+        out["replays"].append({
+            "load": x, "arrival_rate_req_per_s": rate,
+            "batched_fp32": b, "plain_fp64_one_at_a_time": f,
+            "throughput_ratio": b["throughput_req_per_s"] / f["throughput_req_per_s"],
+            "p99_ratio_plain_over_batched": f["p99_ms"] / b["p99_ms"]})
+        print("  batched p50 %.0f p99 %.0f ms %.2f req/s | plain FP64 p50 %.0f p99 %.0f ms "
+              "%.2f req/s" % (b["p50_ms"], b["p99_ms"], b["throughput_req_per_s"], f["p50_ms"],
+                              f["p99_ms"], f["throughput_req_per_s"]), file=sys.stderr,
+              flush=True)
+    if log is not None:
+        log.close()
+    out["workload"] = ("serving mix: the first %d of %d requests (seed 512), N in 2..14, D in 2..5, "
+                       "M in 0..1, population or 3-direction absorption, %d RK4 steps of 1 fs; "
+                       "Poisson arrivals at 0.5x, 0.8x, 1.0x of the batched closed-loop capacity"
+                       % (n, len(mix), args.serve_steps))
+    return out
+
+
+def run_serve(args):
+    """The serving leg on its own, as one JSON line."""
+    sv = serve_leg(args)
+    r1 = sv["replays"][-1]["batched_fp32"]
     line = {
         "metric": METRIC,
-        "value": work_b / span_b,
+        "value": r1["ado_updates_per_s"],
         "unit": "ADO-updates/s",
         "n_gpus": 1,
         "steps": args.serve_steps,
@@ -293,25 +384,9 @@ def run_serve(args):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": "serving mix: %d requests (seed 512), N in 2..14, D in 2..5, M in 0..1, "
-                        "population or 3-direction absorption, %d RK4 steps of 1 fs, Poisson "
-                        "arrivals at %.2fx the closed-loop capacity" % (
-                            len(reqs), args.serve_steps, args.serve_load),
-            "slots": args.serve_slots, "arena_GB": args.serve_arena_gb,
-        },
-        "serve": {
-            "capacity_req_per_s": capacity,
-            "arrival_rate_req_per_s": rate,
-            "batched_fp32": {"p50_ms": 1e3 * _percentile(lat_b, 50),
-                             "p99_ms": 1e3 * _percentile(lat_b, 99),
-                             "throughput_req_per_s": len(reqs) / span_b,
-                             "ado_updates_per_s": work_b / span_b},
-            "plain_fp64_one_at_a_time": {"p50_ms": 1e3 * _percentile(lat_f, 50),
-                                         "p99_ms": 1e3 * _percentile(lat_f, 99),
-                                         "throughput_req_per_s": len(reqs) / span_f,
-                                         "ado_updates_per_s": work_f / span_f},
-        },
+        "config": {"workload": sv["workload"], "slots": args.serve_slots,
+                   "arena_GB": args.serve_arena_gb},
+        "serve": sv,
         "roofline": None,
         "cpu_baseline": None,
     }
@@ -509,6 +584,12 @@ def main():
     if args.cpu_baseline_seconds > 0:
         cpu = cpu_baseline(prob, args.cpu_baseline_seconds)
 
+    serve = None
+    if args.serve_seconds > 0:
+        work = st = h = None  # the 48-site state and stage copies leave the device
+        torch.cuda.empty_cache()
+        serve = serve_leg(args)
+
     line = {
         "metric": METRIC,
         "value": ado_updates,
@@ -546,6 +627,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "fp64": fp64,
+        "serve": serve,
     }
     print(json.dumps(line), flush=True)
 
