@@ -318,6 +318,14 @@ heom_status heom_destroy(heom_hierarchy* h);
  * ADO array, i.e. 2/3/3/5 passes for stages 1..4; neighbour reads counted
  * once), and optionally resets the counters. */
 heom_status heom_timing_enable(int32_t enable);
+/* Launch-shape override, for tests and tuning (process-wide; 0 = the
+ * library's choice).  max_workgroups caps the number of workers of the
+ * persistent stage kernel; max_ados_per_tile caps the ADOs one workgroup of
+ * the FMA stage kernel takes (applied when a propagation or a server request
+ * binds its workspace).  Every element is computed by the same arithmetic in
+ * any shape, so results do not change, bit for bit.  Negative values:
+ * HEOM_E_INVAL. */
+heom_status heom_set_launch_shape(int32_t max_workgroups, int32_t max_ados_per_tile);
 heom_status heom_timing_read(double* bulk_ms, int64_t* bulk_launches, double* bulk_bytes,
                              int32_t reset);
 

@@ -261,7 +261,7 @@ class Hierarchy:
         y[0] = torch.as_tensor(np.asarray(mu3, np.float64).T.astype(np.complex128))
         return y
 
-    def propagate_block(self, y, dt_fs, n_steps, record_every, obs, stream=None):
+    def propagate_block(self, y, dt_fs, n_steps, record_every, obs, stream=None, work=None):
         """heom_propagate_block; returns the correlations P [n_rec, 3] (complex)."""
         torch = _torch()
         o = np.ascontiguousarray(obs, dtype=np.float64)
@@ -269,11 +269,14 @@ class Hierarchy:
             raise ValueError("obs must be [3][N]")
         info = _info_struct(self.info)
         nb = load().heom_block_work_bytes(ctypes.byref(info), int(n_steps), int(record_every))
-        work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        if work is None:
+            work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        if work.numel() < nb:
+            raise ValueError("block workspace smaller than heom_block_work_bytes")
         n_rec = load().heom_record_count(n_steps, record_every)
         rec = np.zeros((n_rec, 6))
         check(load().heom_propagate_block(self.handle, ctypes.c_void_p(y.data_ptr()),
-                                          ctypes.c_void_p(work.data_ptr()), nb, float(dt_fs),
+                                          ctypes.c_void_p(work.data_ptr()), work.numel(), float(dt_fs),
                                           int(n_steps), int(record_every), o.ctypes.data,
                                           rec.ctypes.data, _stream_handle(stream)))
         return rec[:, 0::2] + 1j * rec[:, 1::2]
@@ -291,6 +294,12 @@ class Hierarchy:
         hr = np.ascontiguousarray(host_rest, dtype=self._host_rest_dtype)
         check(load().heom_set_state(self.handle, self._st(state), h0.ctypes.data,
                                     hr.ctypes.data if hr.size else None, _stream_handle()))
+
+
+def set_launch_shape(max_workgroups=0, max_ados_per_tile=0):
+    """heom_set_launch_shape: cap the persistent kernel's workers and the FMA
+    kernel's ADOs per workgroup (0 = the library's choice)."""
+    check(load().heom_set_launch_shape(int(max_workgroups), int(max_ados_per_tile)))
 
 
 def cd_vectors(R, d):

@@ -98,6 +98,7 @@ SIGNATURES = {
     "heom_destroy": (i32, [vp]),
     "heom_spectrum": (i32, [vp, i32, i64, f64, vp, i64, vp]),
     "heom_timing_enable": (i32, [i32]),
+    "heom_set_launch_shape": (i32, [i32, i32]),
     "heom_timing_read": (i32, [P(f64), P(i64), P(f64), i32]),
     "heom_server_create": (i32, [vp, sz, i32, vp, P(vp)]),
     "heom_submit": (i32, [vp, P(HeomRequest), P(u64)]),

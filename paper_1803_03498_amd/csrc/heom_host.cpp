@@ -895,6 +895,14 @@ heom_status heom_propagate_noalloc(const heom_hierarchy* h, heom_state io, doubl
                           hermitian, host_out, stream, false);
 }
 
+heom_status heom_set_launch_shape(int32_t max_workgroups, int32_t max_ados_per_tile) {
+    if (max_workgroups < 0 || max_ados_per_tile < 0)
+        return fail(HEOM_E_INVAL, "launch-shape caps must be >= 0");
+    heom::g_max_workgroups.store(max_workgroups);
+    heom::g_max_ados_per_tile.store(max_ados_per_tile);
+    return HEOM_OK;
+}
+
 heom_status heom_timing_enable(int32_t enable) {
     g_timing.enabled.store(enable != 0);
     return HEOM_OK;

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -98,6 +99,9 @@ struct StageSpec {
     // then "-" rows and columns are read from the packed ADOs).
     int32_t mirror_in, mirror_out;
 };
+
+// Launch-shape caps (heom_set_launch_shape; 0 = none).
+extern std::atomic<int> g_max_workgroups, g_max_ados_per_tile;
 
 // One coherence-block request in a batched launch (device job table).
 struct BlockJob {

@@ -1588,10 +1588,14 @@ int bulk_mfma_blocks(int N, bool h_complex, int precision) {
     return (N + 15) / 16;
 }
 
+std::atomic<int> g_max_workgroups{0}, g_max_ados_per_tile{0};
+
 int bulk_ados_per_tile(int N, int W, int D, int tsize) {
     const int NN = N * N;
     const int nt = fma_block(tsize, N);
     int g = NN >= nt ? 1 : nt / NN;
+    const int cap = g_max_ados_per_tile.load();
+    if (cap > 0) g = std::min(g, cap);
     // keep a tile's LDS (matrices plus staged links) within 64 KiB
     while (g > 1 && fma_lds(N, W, D, g, tsize).total > 64 * 1024) --g;
     return g;
@@ -2014,7 +2018,8 @@ static hipError_t launch_persist_t(const Job& single, int total_tiles, const Sta
     hipError_t e = sigma0_ride_along<float, false>(single, nullptr, 1, 1, true, sp, budget, stream,
                                                    &extra, &lds);
     if (e != hipSuccess) return e;
-    const int workers = std::min(total_tiles, resident_workgroups(fn, NT, lds, cap));
+    int workers = std::min(total_tiles, resident_workgroups(fn, NT, lds, cap));
+    if (g_max_workgroups.load() > 0) workers = std::min(workers, g_max_workgroups.load());
     hipLaunchKernelGGL((k_stage_persist<NB, NBASE, VEC>), dim3(extra + workers), dim3(NT), lds,
                        stream, single, sp, total_tiles, extra, (unsigned)lds);
     return hipGetLastError();
