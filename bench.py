@@ -56,7 +56,7 @@ def _mix_largest():
     return run
 
 
-KERNEL_SOURCES = ("heom_kernels.hip", "heom_stage_persist.inc")
+KERNEL_SOURCES = ("heom_kernels.hip", "heom_stage_persist.inc", "heom_stage_small.inc")
 
 
 def _kernel_source_digest():
@@ -170,7 +170,8 @@ def _bulk_kernel_name(info, precision, N, heom):
     if precision == heom.FP32_MIXED and 10 <= N <= 64:
         return "k_stage_persist"
     if not info["bulk_kernel"]:
-        return "k_bulk_fma"
+        # single propagations with N <= 16 take the persistent FMA kernel
+        return "k_stage_small" if N <= 16 else "k_bulk_fma"
     return "k_bulk_mfma_pk" if precision == heom.FP32_HERM else "k_bulk_mfma"
 
 

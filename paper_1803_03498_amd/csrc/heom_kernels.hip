@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <atomic>
 #include <mutex>
+#include <type_traits>
 
 #include "heom_internal.h"
 
@@ -519,6 +520,131 @@ __device__ __forceinline__ T h_entry(const Tables& t, int idx) {
 // global memory where they are used.
 constexpr int kPrefRows = 4;
 
+// LDS view of an FMA-path tile of GA ADOs (layout fma_lds).
+template <typename T>
+struct FmaTile {
+    T *sH, *sS, *sMml, *sMmc, *sPa, *sGam, *sDelta;
+    int *sMnb, *sMsite, *sPnb, *sLev, *sBegin, *sModes;
+    __device__ FmaTile(char* smem, const FmaLds& L, int N, int W, int Dm, int GA) {
+        sH = reinterpret_cast<T*>(smem + L.h);     // 2*NN
+        sS = reinterpret_cast<T*>(smem + L.s);     // 2*GA*NN
+        sMml = reinterpret_cast<T*>(smem + L.mw);  // [GA][Dm]
+        sMmc = sMml + GA * Dm;
+        sPa = reinterpret_cast<T*>(smem + L.pw);   // [GA][W]
+        sGam = sPa + GA * W;                       // [GA]
+        sDelta = sGam + GA;                        // [N]
+        sMnb = reinterpret_cast<int*>(smem + L.mi);  // [GA][Dm]
+        sMsite = sMnb + GA * Dm;
+        sPnb = reinterpret_cast<int*>(smem + L.pi);  // [GA][W]
+        sLev = reinterpret_cast<int*>(smem + L.lev);
+        sBegin = reinterpret_cast<int*>(smem + L.st);  // [N+1]
+        sModes = sBegin + N + 1;                       // [W]
+    }
+};
+
+// The right-hand side at element (i, j) of ADO g of an FMA-path tile (the
+// stage combination aside): -i [H, sigma], the damping and correction
+// terms, and the coupling lines.  sr, si: the element itself.
+//
+// The neighbour elements are gathered in batches of KB loads that are all
+// issued before the first is used, so a thread keeps several scattered
+// loads in flight instead of waiting on each in turn.  With S0 false (no
+// level-1 ADO in the tile, so no "-" neighbour is the complex128 sigma_0)
+// every load reads the bulk array unconditionally: slots without a
+// contributing link read a valid element and are dropped afterwards.
+template <typename T, bool S0>
+__device__ __forceinline__ void fma_rhs(const FmaTile<T>& V, const NbSrc<T>& nbs, int g, int i,
+                                        int j, int N, int W, int D, int Dm, bool herm, bool hc,
+                                        T sr, T si, T& fr_out, T& fi_out) {
+    const int NN = N * N;
+    const T* S = V.sS + 2 * g * NN;
+    const T* sH = V.sH;
+    T cr = 0, ci = 0;
+    if (hc) {
+        for (int k = 0; k < N; ++k) {
+            const T hr = sH[2 * (i * N + k)], hi = sH[2 * (i * N + k) + 1];
+            const T xr = S[2 * (k * N + j)], xi = S[2 * (k * N + j) + 1];
+            const T yr = S[2 * (i * N + k)], yi = S[2 * (i * N + k) + 1];
+            const T gr = sH[2 * (k * N + j)], gi = sH[2 * (k * N + j) + 1];
+            cr += hr * xr - hi * xi - (yr * gr - yi * gi);
+            ci += hr * xi + hi * xr - (yr * gi + yi * gr);
+        }
+    } else {
+        for (int k = 0; k < N; ++k) {
+            const T hik = sH[2 * (i * N + k)], hkj = sH[2 * (k * N + j)];
+            cr += hik * S[2 * (k * N + j)] - S[2 * (i * N + k)] * hkj;
+            ci += hik * S[2 * (k * N + j) + 1] - S[2 * (i * N + k) + 1] * hkj;
+        }
+    }
+    const T gm = V.sGam[g] + ((i != j) ? V.sDelta[i] + V.sDelta[j] : (T)0);
+    T fr = ci - gm * sr, fi = -cr - gm * si;
+    constexpr int KB = sizeof(T) == 4 ? 8 : 4;
+    auto nb_elem = [&](int nb, int r, int c) -> cpx<T> {
+        if constexpr (S0) return load_nb<T>(nbs, nb, r, c);
+        else return ld<T>(nbs.rest, (size_t)(nb - 1) * NN + (size_t)r * N + c);
+    };
+    // "-" links that touch row or column i, j
+    for (int a0 = 0; a0 < Dm; a0 += KB) {
+        cpx<T> xs[KB];
+#pragma unroll
+        for (int q = 0; q < KB; ++q) {
+            const int a = a0 + q;
+            const int s = a < Dm ? V.sMsite[g * Dm + a] : -1;
+            const int nb = a < Dm ? V.sMnb[g * Dm + a] : -1;
+            const bool use = s >= 0 && nb >= 0 && (i == s || j == s);
+            const bool cj = herm && (j == s) && (i != s);
+            if constexpr (S0) {
+                xs[q] = cpx<T>{(T)0, (T)0};
+                if (use) xs[q] = nb_elem(nb, cj ? s : i, cj ? i : j);
+            } else {
+                xs[q] = nb_elem(use ? nb : 1, cj ? s : i, cj ? i : j);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < KB; ++q) {
+            const int a = a0 + q;
+            const int s = a < Dm ? V.sMsite[g * Dm + a] : -1;
+            const int nb = a < Dm ? V.sMnb[g * Dm + a] : -1;
+            if (!(s >= 0 && nb >= 0 && (i == s || j == s))) continue;
+            const cpx<T> x = (herm && (j == s) && (i != s)) ? cconj(xs[q]) : xs[q];
+            const T vx = (T)((i == s) - (j == s)), vo = (T)((i == s) + (j == s));
+            const T thr = V.sMml[g * Dm + a] * vo, thi = V.sMmc[g * Dm + a] * vx;
+            fr += thr * x.re - thi * x.im;
+            fi += thr * x.im + thi * x.re;
+        }
+    }
+    // "+" links (never sigma_0): the modes of state i, then those of state j
+    if (V.sLev[g] < D && i != j) {
+        const int bi = V.sBegin[i], ni = V.sBegin[i + 1] - bi;
+        const int bj = V.sBegin[j], n_all = ni + V.sBegin[j + 1] - bj;
+        for (int k0 = 0; k0 < n_all; k0 += KB) {
+            cpx<T> xs[KB];
+#pragma unroll
+            for (int q = 0; q < KB; ++q) {
+                const int k = min(k0 + q, n_all - 1);
+                const bool on_j = k >= ni;
+                const int l = V.sModes[on_j ? bj + k - ni : bi + k];
+                const bool cj = herm && on_j;
+                xs[q] = ld<T>(nbs.rest, (size_t)(V.sPnb[g * W + l] - 1) * NN +
+                                            (size_t)(cj ? j : i) * N + (cj ? i : j));
+            }
+#pragma unroll
+            for (int q = 0; q < KB; ++q) {
+                const int k = k0 + q;
+                if (k >= n_all) continue;
+                const bool on_j = k >= ni;
+                const int l = V.sModes[on_j ? bj + k - ni : bi + k];
+                const cpx<T> x = (herm && on_j) ? cconj(xs[q]) : xs[q];
+                const T pa = on_j ? -V.sPa[g * W + l] : V.sPa[g * W + l];
+                fr -= pa * x.im;
+                fi += pa * x.re;
+            }
+        }
+    }
+    fr_out = fr;
+    fi_out = fi;
+}
+
 // --------------------------------------------------------------------------
 // Bulk stage kernel, wavefront-FMA path (N < 16, or complex H): a workgroup
 // of fma_block threads takes GA = max(1, fma_block / N^2) consecutive ADOs
@@ -554,20 +680,12 @@ __global__ __launch_bounds__(kFmaMaxBlock) __attribute__((amdgpu_waves_per_eu(
     const int GA = J.ados_per_tile;
     const int u0 = 1 + (b - J.tile_begin) * GA;
     const int n_here = min(GA, t.n_ado - u0);
-    const FmaLds L = fma_lds(N, W, D, GA, (int)sizeof(T));
-    T* sH = reinterpret_cast<T*>(smem_raw + L.h);     // 2*NN
-    T* sS = reinterpret_cast<T*>(smem_raw + L.s);     // 2*GA*NN
-    T* sMml = reinterpret_cast<T*>(smem_raw + L.mw);  // [GA][Dm]
-    T* sMmc = sMml + GA * Dm;
-    T* sPa = reinterpret_cast<T*>(smem_raw + L.pw);   // [GA][W]
-    T* sGam = sPa + GA * W;                           // [GA]
-    T* sDelta = sGam + GA;                            // [N]
-    int* sMnb = reinterpret_cast<int*>(smem_raw + L.mi);  // [GA][Dm]
-    int* sMsite = sMnb + GA * Dm;
-    int* sPnb = reinterpret_cast<int*>(smem_raw + L.pi);  // [GA][W]
-    int* sLev = reinterpret_cast<int*>(smem_raw + L.lev);
-    int* sBegin = reinterpret_cast<int*>(smem_raw + L.st);  // [N+1]
-    int* sModes = sBegin + N + 1;                            // [W]
+    const FmaTile<T> V(smem_raw, fma_lds(N, W, D, GA, (int)sizeof(T)), N, W, Dm, GA);
+    T* sH = V.sH;
+    T* sS = V.sS;
+    T *sMml = V.sMml, *sMmc = V.sMmc, *sPa = V.sPa, *sGam = V.sGam, *sDelta = V.sDelta;
+    int *sMnb = V.sMnb, *sMsite = V.sMsite, *sPnb = V.sPnb, *sLev = V.sLev;
+    int *sBegin = V.sBegin, *sModes = V.sModes;
     const int tid = threadIdx.x;
 
     // stage H, the tile, the per-ADO link data and the per-state tables
@@ -587,20 +705,30 @@ __global__ __launch_bounds__(kFmaMaxBlock) __attribute__((amdgpu_waves_per_eu(
     }
     for (int x = tid; x < n_here * Dm; x += blockDim.x) {
         const size_t at = (size_t)u0 * Dm + x;  // row u0 + x / Dm, entry x % Dm
-        const pair_d w = G(reinterpret_cast<const pair_d*>(t.mlist_w))[at];
         sMnb[x] = G(reinterpret_cast<const pair_i*>(t.mlist))[at].x;
         sMsite[x] = G(t.mlist_site)[at];
-        sMml[x] = (T)w.x;
-        sMmc[x] = (T)w.y;
+        if constexpr (sizeof(T) == 4) {
+            const pair_f w = G(reinterpret_cast<const pair_f*>(t.mlist_w32))[at];
+            sMml[x] = w.x;
+            sMmc[x] = w.y;
+        } else {
+            const pair_d w = G(reinterpret_cast<const pair_d*>(t.mlist_w))[at];
+            sMml[x] = w.x;
+            sMmc[x] = w.y;
+        }
     }
     for (int g = tid; g < n_here; g += blockDim.x) {
         sLev[g] = G(t.level)[u0 + g];
         sGam[g] = (T)G(t.damping)[u0 + g];
     }
-    for (int x = tid; x < n_here * W; x += blockDim.x) {
-        const size_t at = (size_t)u0 * W + x;
-        sPnb[x] = G(t.plus)[at];
-        sPa[x] = (T)G(t.plus_w)[at];
+    // "+" rows: ADOs are stored by level, so a tile whose first ADO is on
+    // the top level has none
+    if (G(t.level)[u0] < D) {
+        for (int x = tid; x < n_here * W; x += blockDim.x) {
+            const size_t at = (size_t)u0 * W + x;
+            sPnb[x] = G(t.plus)[at];
+            sPa[x] = (T)G(t.plus_w)[at];
+        }
     }
     for (int x = tid; x <= N; x += blockDim.x) {
         sBegin[x] = G(t.state_mode_begin)[x];
@@ -620,58 +748,15 @@ __global__ __launch_bounds__(kFmaMaxBlock) __attribute__((amdgpu_waves_per_eu(
     const NbSrc<T> nbs{J.sig0[sp.in], J.rest[sp.in], N};
     const bool herm = J.herm != 0, hc = HC && t.h_complex != 0;
     const T h = (T)(sp.hmul * J.dt), w_in = (T)sp.w_in;
+    const bool s0_tile = sLev[0] <= 1;  // ADOs are stored by level
     for (int e = tid; e < tot; e += blockDim.x) {
         const int g = e / NN;
         const int ij = e - g * NN;
         const int i = ij / N, j = ij - (ij / N) * N;
-        const T* S = sS + 2 * g * NN;
-        // -i [H, sigma]
-        T cr = 0, ci = 0;
-        if (hc) {
-            for (int k = 0; k < N; ++k) {
-                const T hr = sH[2 * (i * N + k)], hi = sH[2 * (i * N + k) + 1];
-                const T xr = S[2 * (k * N + j)], xi = S[2 * (k * N + j) + 1];
-                const T yr = S[2 * (i * N + k)], yi = S[2 * (i * N + k) + 1];
-                const T gr = sH[2 * (k * N + j)], gi = sH[2 * (k * N + j) + 1];
-                cr += hr * xr - hi * xi - (yr * gr - yi * gi);
-                ci += hr * xi + hi * xr - (yr * gi + yi * gr);
-            }
-        } else {
-            for (int k = 0; k < N; ++k) {
-                const T hik = sH[2 * (i * N + k)], hkj = sH[2 * (k * N + j)];
-                cr += hik * S[2 * (k * N + j)] - S[2 * (i * N + k)] * hkj;
-                ci += hik * S[2 * (k * N + j) + 1] - S[2 * (i * N + k) + 1] * hkj;
-            }
-        }
-        const T sr = S[2 * ij], si = S[2 * ij + 1];
-        const T gm = sGam[g] + ((i != j) ? sDelta[i] + sDelta[j] : (T)0);
-        T fr = ci - gm * sr, fi = -cr - gm * si;
-        for (int a = 0; a < Dm; ++a) {
-            const int s = sMsite[g * Dm + a];
-            if (s < 0 || (i != s && j != s)) continue;
-            const int nb = sMnb[g * Dm + a];
-            const bool col = (j == s) && (i != s);
-            const cpx<T> x = (herm && col) ? cconj(load_nb<T>(nbs, nb, s, i))
-                                           : load_nb<T>(nbs, nb, i, j);
-            const T vx = (T)((i == s) - (j == s)), vo = (T)((i == s) + (j == s));
-            const T thr = sMml[g * Dm + a] * vo, thi = sMmc[g * Dm + a] * vx;
-            fr += thr * x.re - thi * x.im;
-            fi += thr * x.im + thi * x.re;
-        }
-        if (sLev[g] < D && i != j) {
-            for (int pass = 0; pass < 2; ++pass) {
-                const int s = pass == 0 ? i : j;
-                for (int m = sBegin[s]; m < sBegin[s + 1]; ++m) {
-                    const int l = sModes[m];
-                    const int nb = sPnb[g * W + l];
-                    const cpx<T> x = (herm && pass == 1) ? cconj(load_nb<T>(nbs, nb, s, i))
-                                                         : load_nb<T>(nbs, nb, i, j);
-                    const T pa = pass == 0 ? sPa[g * W + l] : -sPa[g * W + l];
-                    fr -= pa * x.im;
-                    fi += pa * x.re;
-                }
-            }
-        }
+        const T sr = sS[2 * e], si = sS[2 * e + 1];
+        T fr, fi;
+        if (s0_tile) fma_rhs<T, true>(V, nbs, g, i, j, N, W, D, Dm, herm, hc, sr, si, fr, fi);
+        else fma_rhs<T, false>(V, nbs, g, i, j, N, W, D, Dm, herm, hc, sr, si, fr, fi);
         T yr = w_in * sr + h * fr, yi = w_in * si + h * fi;
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
@@ -1202,6 +1287,7 @@ __global__ __launch_bounds__((128 * NB * mfma_ados_per_wg<T, NB>())) __attribute
 
 
 #include "heom_stage_persist.inc"
+#include "heom_stage_small.inc"
 
 // Bulk RK4 stage on Hermitian-packed FP32 storage (P as defined at pk_nb).
 // Same thread layout and matrix-core product as k_bulk_mfma on its
@@ -2104,6 +2190,54 @@ static hipError_t launch_fma_t(const Job& single, const Job* jobs_dev, int n_job
     return hipGetLastError();
 }
 
+// ADOs per tile of the persistent FMA kernel for a single job (and its
+// LDS), or 0 when the job is not for it: N <= 16, and the tile's link rows
+// within the kernel's register slots.
+static int small_ados_per_tile(const Job& single, int tsize, size_t* lds) {
+    const int N = single.t.N, NN = N * N, W = single.t.W, D = single.t.D, Dm = std::max(D, 1);
+    if (N > 16 || Dm > 256 || W > 256) return 0;
+    int GA = std::max(1, 256 / NN);
+    const int cap = g_max_ados_per_tile.load();
+    if (cap > 0) GA = std::min(GA, cap);
+    while (GA > 1 && (GA * Dm > 256 || GA * W > 256 || fma_lds(N, W, D, GA, tsize).total > 64 * 1024))
+        --GA;
+    *lds = fma_lds(N, W, D, GA, tsize).total;
+    return GA;
+}
+
+template <typename T, bool HC, int NBASE>
+static hipError_t launch_small_t(const Job& single, const StageSpec& sp, int GA, size_t lds,
+                                 hipStream_t stream) {
+    const void* fn = reinterpret_cast<const void*>(&k_stage_small<T, HC, NBASE>);
+    static std::once_flag attr_once;
+    static hipError_t attr_err = hipSuccess;
+    if (allow_full_lds(attr_once, attr_err, fn) != hipSuccess) return attr_err;
+    const int n_tiles = (single.t.n_ado - 1 + GA - 1) / GA;
+    // sigma_0 rides along in FP32 only, as in the FMA kernel
+    int extra = 0;
+    size_t lds_launch = lds;
+    hipError_t e = sigma0_ride_along<T, false>(single, nullptr, 1, 1, sizeof(T) == 4, sp,
+                                               160 * 1024 / 8, stream, &extra, &lds_launch);
+    if (e != hipSuccess) return e;
+    int workers = std::min(n_tiles, resident_workgroups(fn, 256, lds_launch, 8));
+    if (g_max_workgroups.load() > 0) workers = std::min(workers, g_max_workgroups.load());
+    hipLaunchKernelGGL((k_stage_small<T, HC, NBASE>), dim3(extra + workers), dim3(256), lds_launch,
+                       stream, single, sp, GA, n_tiles, extra, (unsigned)lds_launch);
+    return hipGetLastError();
+}
+
+template <typename T, bool HC>
+static hipError_t launch_small_hc(const Job& single, const StageSpec& sp, int GA, size_t lds,
+                                  hipStream_t stream) {
+    switch (sp.nbase) {
+        case 0: return launch_small_t<T, HC, 0>(single, sp, GA, lds, stream);
+        case 1: return launch_small_t<T, HC, 1>(single, sp, GA, lds, stream);
+        case 2: return launch_small_t<T, HC, 2>(single, sp, GA, lds, stream);
+        case 3: return launch_small_t<T, HC, 3>(single, sp, GA, lds, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 thread_local const char* g_launch_what = "";
 
 template <typename T>
@@ -2149,6 +2283,13 @@ static hipError_t launch_stage_t(const Job& single, const Job* jobs_dev, int n_j
         if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
         e = launch_mfma<T>(nb, single.herm != 0, single, jobs_dev, n_jobs, total_tiles, sp, stream, n_s0);
         if (e != hipSuccess) g_launch_what = "MFMA bulk stage kernel";
+    } else if (size_t lds_small = 0;
+               !batched && small_ados_per_tile(single, (int)sizeof(T), &lds_small) > 0) {
+        if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
+        const int GA = small_ados_per_tile(single, (int)sizeof(T), &lds_small);
+        e = single.t.h_complex ? launch_small_hc<T, true>(single, sp, GA, lds_small, stream)
+                               : launch_small_hc<T, false>(single, sp, GA, lds_small, stream);
+        if (e != hipSuccess) g_launch_what = "persistent FMA stage kernel";
     } else {
         if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
         // batched launches carry the largest tile LDS of the batch
