@@ -170,8 +170,9 @@ def _bulk_kernel_name(info, precision, N, heom):
     if precision == heom.FP32_MIXED and 10 <= N <= 64:
         return "k_stage_persist"
     if not info["bulk_kernel"]:
-        # single propagations with N <= 16 take the persistent FMA kernel
-        return "k_stage_small" if N <= 16 else "k_bulk_fma"
+        # single propagations with N <= 16 and >= 32768 ADOs take the
+        # persistent FMA kernel
+        return "k_stage_small" if N <= 16 and info["n_ado"] >= 32768 else "k_bulk_fma"
     return "k_bulk_mfma_pk" if precision == heom.FP32_HERM else "k_bulk_mfma"
 
 

@@ -168,6 +168,32 @@ __host__ __device__ inline FmaLds fma_lds(int N, int W, int D, int GA, int tsize
     return L;
 }
 
+// LDS of the persistent FMA kernel (k_stage_small) for tiles of GA ADOs:
+// launch-wide tables (H, correction coefficients, per-state mode lists and
+// mode states), one row buffer and two slots of tile elements and link
+// tables.  W = 0 for the top-level launch (no "+" links).  Offsets in
+// bytes, 16-byte aligned.
+struct SmallLds {
+    size_t h, delta, begin, rows, slot0, slot_bytes, total;
+};
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+__host__ __device__ inline SmallLds small_lds(int N, int W, int D, int GA, int tsize, bool herm) {
+    const size_t Dm = D > 0 ? D : 1, NN = (size_t)N * N, G = GA;
+    SmallLds L{};
+    size_t o = 0;
+    L.h = o; o = align16(o + 2 * NN * tsize);
+    L.delta = o; o = align16(o + (size_t)N * tsize);
+    L.begin = o; o = align16(o + (size_t)(N + 1 + 2 * W) * 4);
+    L.rows = o; o = align16(o + 2 * G * (Dm + W) * N * (herm ? 1 : 2) * tsize);
+    L.slot_bytes = align16((size_t)tsize * (2 * G * NN + 2 * G * Dm + G * W + G) +
+                           4 * (2 * G * Dm + G * W));
+    L.slot0 = o; o += 2 * L.slot_bytes;
+    L.total = o;
+    return L;
+}
+
 // ADOs per FMA-path tile: fma_block / N^2 threads' worth, reduced to fit 64 KiB of LDS.
 int bulk_ados_per_tile(int N, int W, int D, int tsize);
 // Device address and size of this device's static scratch array (looked up

@@ -2190,50 +2190,98 @@ static hipError_t launch_fma_t(const Job& single, const Job* jobs_dev, int n_job
     return hipGetLastError();
 }
 
-// ADOs per tile of the persistent FMA kernel for a single job (and its
-// LDS), or 0 when the job is not for it: N <= 16, and the tile's link rows
-// within the kernel's register slots.
-static int small_ados_per_tile(const Job& single, int tsize, size_t* lds) {
-    const int N = single.t.N, NN = N * N, W = single.t.W, D = single.t.D, Dm = std::max(D, 1);
-    if (N > 16 || Dm > 256 || W > 256) return 0;
+// Tile size of one launch of the persistent FMA kernel (and its LDS), or 0
+// when it does not fit: one slot of each link table per thread, the tile's
+// neighbour rows within rq per thread, and the LDS within the share of a CU
+// that the kernel's occupancy leaves to each workgroup.  plus: the launch
+// over the ADOs below the top level.
+static int small_tile(const Job& single, int tsize, bool plus, int rq, size_t budget, size_t* lds) {
+    const int N = single.t.N, NN = N * N, W = plus ? single.t.W : 0, D = single.t.D;
+    const int Dm = std::max(D, 1);
+    const bool herm = single.herm != 0;
+    auto fits = [&](int GA) {
+        return GA * Dm <= 256 && GA * W <= 256 && GA * (Dm + W) * N * (herm ? 1 : 2) <= 256 * rq &&
+               small_lds(N, W, D, GA, tsize, herm).total <= budget;
+    };
     int GA = std::max(1, 256 / NN);
     const int cap = g_max_ados_per_tile.load();
     if (cap > 0) GA = std::min(GA, cap);
-    while (GA > 1 && (GA * Dm > 256 || GA * W > 256 || fma_lds(N, W, D, GA, tsize).total > 64 * 1024))
-        --GA;
-    *lds = fma_lds(N, W, D, GA, tsize).total;
+    while (GA > 1 && !fits(GA)) --GA;
+    if (!fits(GA)) return 0;
+    *lds = small_lds(N, W, D, GA, tsize, herm).total;
     return GA;
 }
 
-template <typename T, bool HC, int NBASE>
-static hipError_t launch_small_t(const Job& single, const StageSpec& sp, int GA, size_t lds,
-                                 hipStream_t stream) {
-    const void* fn = reinterpret_cast<const void*>(&k_stage_small<T, HC, NBASE>);
+constexpr int kSmallRqPlus = 4, kSmallRqTop = 2;
+
+// LDS per workgroup when `per_cu` workgroups share a CU's 160 KiB.
+static size_t small_lds_budget(int per_cu) { return (size_t)(160 * 1024 / per_cu) & ~(size_t)1023; }
+
+// The persistent FMA kernel takes single jobs with N <= 16 and at least
+// kSmallMinAdos ADOs whose tiles fit both of its launches.  Smaller
+// hierarchies take the one-launch FMA kernel: with a few thousand ADOs the
+// launches, not the memory traffic, set the time (FMO-like, 3060 ADOs of
+// 7 x 7: 9.5 against 20 us per stage).
+constexpr int kSmallMinAdos = 32768;
+
+static bool small_eligible(const Job& single, int tsize) {
+    if (single.t.N > 16 || single.t.D < 1 || single.t.n_ado < kSmallMinAdos) return false;
+    size_t l;
+    const size_t bp = small_lds_budget(tsize == 4 ? small_waves<float, true>() : small_waves<double, true>());
+    const size_t bt = small_lds_budget(tsize == 4 ? small_waves<float, false>() : small_waves<double, false>());
+    return small_tile(single, tsize, false, kSmallRqTop, bt, &l) > 0 &&
+           (single.n_low == 0 || small_tile(single, tsize, true, kSmallRqPlus, bp, &l) > 0);
+}
+
+template <typename T, bool HERM, int NBASE, bool PLUS, int RQ>
+static hipError_t launch_small_part(const Job& single, const StageSpec& sp, int u_begin, int u_end,
+                                    bool carry_s0, hipStream_t stream) {
+    const void* fn = reinterpret_cast<const void*>(&k_stage_small<T, true, HERM, NBASE, PLUS, RQ>);
     static std::once_flag attr_once;
     static hipError_t attr_err = hipSuccess;
     if (allow_full_lds(attr_once, attr_err, fn) != hipSuccess) return attr_err;
-    const int n_tiles = (single.t.n_ado - 1 + GA - 1) / GA;
-    // sigma_0 rides along in FP32 only, as in the FMA kernel
+    const int tsize = (int)sizeof(T);
+    constexpr int per_cu = small_waves<T, PLUS>();
+    size_t lds = 0;
+    const int GA = small_tile(single, tsize, PLUS, RQ, small_lds_budget(per_cu), &lds);
+    if (GA < 1) return hipErrorInvalidValue;
+    const int n_tiles = (u_end - u_begin + GA - 1) / GA;
+    // sigma_0 rides along with one of the launches, in FP32 only (as in the FMA kernel)
     int extra = 0;
     size_t lds_launch = lds;
-    hipError_t e = sigma0_ride_along<T, false>(single, nullptr, 1, 1, sizeof(T) == 4, sp,
-                                               160 * 1024 / 8, stream, &extra, &lds_launch);
-    if (e != hipSuccess) return e;
-    int workers = std::min(n_tiles, resident_workgroups(fn, 256, lds_launch, 8));
+    if (carry_s0) {
+        hipError_t e = sigma0_ride_along<T, false>(single, nullptr, 1, 1, sizeof(T) == 4, sp,
+                                                   160 * 1024 / per_cu, stream, &extra, &lds_launch);
+        if (e != hipSuccess) return e;
+    }
+    int workers = std::min(n_tiles, resident_workgroups(fn, 256, lds_launch, per_cu));
     if (g_max_workgroups.load() > 0) workers = std::min(workers, g_max_workgroups.load());
-    hipLaunchKernelGGL((k_stage_small<T, HC, NBASE>), dim3(extra + workers), dim3(256), lds_launch,
-                       stream, single, sp, GA, n_tiles, extra, (unsigned)lds_launch);
+    hipLaunchKernelGGL((k_stage_small<T, true, HERM, NBASE, PLUS, RQ>), dim3(extra + workers),
+                       dim3(256), lds_launch, stream, single, sp, u_begin, u_end, GA, extra,
+                       (unsigned)lds_launch);
     return hipGetLastError();
 }
 
-template <typename T, bool HC>
-static hipError_t launch_small_hc(const Job& single, const StageSpec& sp, int GA, size_t lds,
-                                  hipStream_t stream) {
+template <typename T, bool HERM, int NBASE>
+static hipError_t launch_small_n(const Job& single, const StageSpec& sp, hipStream_t stream) {
+    const int top_first = 1 + single.n_low;
+    hipError_t e = hipSuccess;
+    if (single.n_low > 0)
+        e = launch_small_part<T, HERM, NBASE, true, kSmallRqPlus>(single, sp, 1, top_first, false,
+                                                                   stream);
+    if (e == hipSuccess)
+        e = launch_small_part<T, HERM, NBASE, false, kSmallRqTop>(single, sp, top_first,
+                                                                   single.t.n_ado, true, stream);
+    return e;
+}
+
+template <typename T, bool HERM>
+static hipError_t launch_small_h(const Job& single, const StageSpec& sp, hipStream_t stream) {
     switch (sp.nbase) {
-        case 0: return launch_small_t<T, HC, 0>(single, sp, GA, lds, stream);
-        case 1: return launch_small_t<T, HC, 1>(single, sp, GA, lds, stream);
-        case 2: return launch_small_t<T, HC, 2>(single, sp, GA, lds, stream);
-        case 3: return launch_small_t<T, HC, 3>(single, sp, GA, lds, stream);
+        case 0: return launch_small_n<T, HERM, 0>(single, sp, stream);
+        case 1: return launch_small_n<T, HERM, 1>(single, sp, stream);
+        case 2: return launch_small_n<T, HERM, 2>(single, sp, stream);
+        case 3: return launch_small_n<T, HERM, 3>(single, sp, stream);
         default: return hipErrorInvalidValue;
     }
 }
@@ -2283,12 +2331,10 @@ static hipError_t launch_stage_t(const Job& single, const Job* jobs_dev, int n_j
         if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
         e = launch_mfma<T>(nb, single.herm != 0, single, jobs_dev, n_jobs, total_tiles, sp, stream, n_s0);
         if (e != hipSuccess) g_launch_what = "MFMA bulk stage kernel";
-    } else if (size_t lds_small = 0;
-               !batched && small_ados_per_tile(single, (int)sizeof(T), &lds_small) > 0) {
+    } else if (!batched && small_eligible(single, (int)sizeof(T))) {
         if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;
-        const int GA = small_ados_per_tile(single, (int)sizeof(T), &lds_small);
-        e = single.t.h_complex ? launch_small_hc<T, true>(single, sp, GA, lds_small, stream)
-                               : launch_small_hc<T, false>(single, sp, GA, lds_small, stream);
+        e = single.herm ? launch_small_h<T, true>(single, sp, stream)
+                        : launch_small_h<T, false>(single, sp, stream);
         if (e != hipSuccess) g_launch_what = "persistent FMA stage kernel";
     } else {
         if (ev_begin && (e = hipEventRecord(ev_begin, stream)) != hipSuccess) return e;

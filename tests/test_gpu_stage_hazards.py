@@ -12,9 +12,9 @@
   bit: no result depends on which workgroup computes which element.
 
 Cases cover every stage kernel: FMA (FP32 and FP64, Hermitian and not,
-complex H), MFMA (FP64, FP32 non-Hermitian), the persistent kernel (one, two
-and three 16-row blocks), the Hermitian-packed kernel and the
-coherence-block form.
+complex H), the persistent FMA kernel (FP32, FP64 non-Hermitian), MFMA
+(FP64, FP32 non-Hermitian), the persistent MFMA kernel (one, two and three
+16-row blocks), the Hermitian-packed kernel and the coherence-block form.
 """
 
 import numpy as np
@@ -47,6 +47,8 @@ def _cases():
     r33 = hi.random_problem(63, 33, M=0, D=2)
     r12 = hi.random_problem(64, 12, M=1, D=2)
     r9c = hi.random_problem(65, 9, M=1, D=2, complex_h=True)
+    r8 = hi.random_problem(67, 8, M=1, D=6)     # 74613 ADOs: persistent FMA kernel
+    r7 = hi.random_problem(68, 7, M=1, D=6)     # 38760 ADOs
     r18c = hi.random_problem(66, 18, M=0, D=2, complex_h=True)
     pop = lambda p, N: dict(p, dt_fs=0.5, n_steps=5, record_every=1,
                             rho0=hi.population_rho0(N, N // 2), observable={"kind": "population"})
@@ -58,6 +60,8 @@ def _cases():
         ("absorption FMA fp64 non-Hermitian", absn, 0, False),
         ("N=9 complex H FMA fp32", pop(r9c, 9), 1, True),
         ("N=18 complex H FMA fp64", pop(r18c, 18), 0, True),
+        ("N=8 D=6 persistent FMA fp32", pop(r8, 8), 1, True),
+        ("N=7 D=6 persistent FMA fp64 non-Hermitian", pop(r7, 7), 0, False),
         ("N=16 MFMA fp64", pop(r16, 16), 0, True),
         ("N=20 MFMA fp32 non-Hermitian", pop(r20, 20), 1, False),
         ("N=12 persistent fp32", pop(r12, 12), 1, True),
