@@ -171,15 +171,17 @@ __host__ __device__ inline FmaLds fma_lds(int N, int W, int D, int GA, int tsize
 // LDS of the persistent FMA kernel (k_stage_small) for tiles of GA ADOs:
 // launch-wide tables (H, correction coefficients, per-state mode lists and
 // mode states), one row buffer and two slots of tile elements and link
-// tables.  W = 0 for the top-level launch (no "+" links).  Offsets in
+// tables, and el > 1 elements per thread a partial-result slot per element
+// and thread.  W = 0 for the top-level launch (no "+" links).  Offsets in
 // bytes, 16-byte aligned.
 struct SmallLds {
-    size_t h, delta, begin, rows, slot0, slot_bytes, total;
+    size_t h, delta, begin, rows, part, slot0, slot_bytes, total;
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-__host__ __device__ inline SmallLds small_lds(int N, int W, int D, int GA, int tsize, bool herm) {
+__host__ __device__ inline SmallLds small_lds(int N, int W, int D, int GA, int tsize, bool herm,
+                                              int el) {
     const size_t Dm = D > 0 ? D : 1, NN = (size_t)N * N, G = GA;
     SmallLds L{};
     size_t o = 0;
@@ -187,6 +189,7 @@ __host__ __device__ inline SmallLds small_lds(int N, int W, int D, int GA, int t
     L.delta = o; o = align16(o + (size_t)N * tsize);
     L.begin = o; o = align16(o + (size_t)(N + 1 + 2 * W) * 4);
     L.rows = o; o = align16(o + 2 * G * (Dm + W) * N * (herm ? 1 : 2) * tsize);
+    L.part = o; o = align16(o + (el > 1 ? 2 * (size_t)el * 256 * tsize : 0));
     L.slot_bytes = align16((size_t)tsize * (2 * G * NN + 2 * G * Dm + G * W + G) +
                            4 * (2 * G * Dm + G * W));
     L.slot0 = o; o += 2 * L.slot_bytes;

@@ -2195,24 +2195,29 @@ static hipError_t launch_fma_t(const Job& single, const Job* jobs_dev, int n_job
 // neighbour rows within rq per thread, and the LDS within the share of a CU
 // that the kernel's occupancy leaves to each workgroup.  plus: the launch
 // over the ADOs below the top level.
-static int small_tile(const Job& single, int tsize, bool plus, int rq, size_t budget, size_t* lds) {
+static int small_tile(const Job& single, int tsize, bool plus, int rq, int el, size_t budget,
+                      size_t* lds) {
     const int N = single.t.N, NN = N * N, W = plus ? single.t.W : 0, D = single.t.D;
     const int Dm = std::max(D, 1);
     const bool herm = single.herm != 0;
     auto fits = [&](int GA) {
-        return GA * Dm <= 256 && GA * W <= 256 && GA * (Dm + W) * N * (herm ? 1 : 2) <= 256 * rq &&
-               small_lds(N, W, D, GA, tsize, herm).total <= budget;
+        return GA * NN <= 256 * el && GA * Dm <= 256 && GA * W <= 256 &&
+               GA * (Dm + W) * N * (herm ? 1 : 2) <= 256 * rq &&
+               small_lds(N, W, D, GA, tsize, herm, el).total <= budget;
     };
-    int GA = std::max(1, 256 / NN);
+    int GA = std::max(1, 256 * el / NN);
     const int cap = g_max_ados_per_tile.load();
     if (cap > 0) GA = std::min(GA, cap);
     while (GA > 1 && !fits(GA)) --GA;
     if (!fits(GA)) return 0;
-    *lds = small_lds(N, W, D, GA, tsize, herm).total;
+    *lds = small_lds(N, W, D, GA, tsize, herm, el).total;
     return GA;
 }
 
 constexpr int kSmallRqPlus = 4, kSmallRqTop = 2;
+// elements per thread: the top-level launch takes two (twice the ADOs per
+// tile for the same per-tile overhead)
+constexpr int kSmallElPlus = 1, kSmallElTop = 2;
 
 // LDS per workgroup when `per_cu` workgroups share a CU's 160 KiB.
 static size_t small_lds_budget(int per_cu) { return (size_t)(160 * 1024 / per_cu) & ~(size_t)1023; }
@@ -2229,21 +2234,22 @@ static bool small_eligible(const Job& single, int tsize) {
     size_t l;
     const size_t bp = small_lds_budget(tsize == 4 ? small_waves<float, true>() : small_waves<double, true>());
     const size_t bt = small_lds_budget(tsize == 4 ? small_waves<float, false>() : small_waves<double, false>());
-    return small_tile(single, tsize, false, kSmallRqTop, bt, &l) > 0 &&
-           (single.n_low == 0 || small_tile(single, tsize, true, kSmallRqPlus, bp, &l) > 0);
+    return small_tile(single, tsize, false, kSmallRqTop, kSmallElTop, bt, &l) > 0 &&
+           (single.n_low == 0 ||
+            small_tile(single, tsize, true, kSmallRqPlus, kSmallElPlus, bp, &l) > 0);
 }
 
-template <typename T, bool HERM, int NBASE, bool PLUS, int RQ>
+template <typename T, bool HERM, int NBASE, bool PLUS, int RQ, int EL>
 static hipError_t launch_small_part(const Job& single, const StageSpec& sp, int u_begin, int u_end,
                                     bool carry_s0, hipStream_t stream) {
-    const void* fn = reinterpret_cast<const void*>(&k_stage_small<T, true, HERM, NBASE, PLUS, RQ>);
+    const void* fn = reinterpret_cast<const void*>(&k_stage_small<T, true, HERM, NBASE, PLUS, RQ, EL>);
     static std::once_flag attr_once;
     static hipError_t attr_err = hipSuccess;
     if (allow_full_lds(attr_once, attr_err, fn) != hipSuccess) return attr_err;
     const int tsize = (int)sizeof(T);
     constexpr int per_cu = small_waves<T, PLUS>();
     size_t lds = 0;
-    const int GA = small_tile(single, tsize, PLUS, RQ, small_lds_budget(per_cu), &lds);
+    const int GA = small_tile(single, tsize, PLUS, RQ, EL, small_lds_budget(per_cu), &lds);
     if (GA < 1) return hipErrorInvalidValue;
     const int n_tiles = (u_end - u_begin + GA - 1) / GA;
     // sigma_0 rides along with one of the launches, in FP32 only (as in the FMA kernel)
@@ -2256,7 +2262,7 @@ static hipError_t launch_small_part(const Job& single, const StageSpec& sp, int 
     }
     int workers = std::min(n_tiles, resident_workgroups(fn, 256, lds_launch, per_cu));
     if (g_max_workgroups.load() > 0) workers = std::min(workers, g_max_workgroups.load());
-    hipLaunchKernelGGL((k_stage_small<T, true, HERM, NBASE, PLUS, RQ>), dim3(extra + workers),
+    hipLaunchKernelGGL((k_stage_small<T, true, HERM, NBASE, PLUS, RQ, EL>), dim3(extra + workers),
                        dim3(256), lds_launch, stream, single, sp, u_begin, u_end, GA, extra,
                        (unsigned)lds_launch);
     return hipGetLastError();
@@ -2267,11 +2273,11 @@ static hipError_t launch_small_n(const Job& single, const StageSpec& sp, hipStre
     const int top_first = 1 + single.n_low;
     hipError_t e = hipSuccess;
     if (single.n_low > 0)
-        e = launch_small_part<T, HERM, NBASE, true, kSmallRqPlus>(single, sp, 1, top_first, false,
-                                                                   stream);
+        e = launch_small_part<T, HERM, NBASE, true, kSmallRqPlus, kSmallElPlus>(
+            single, sp, 1, top_first, false, stream);
     if (e == hipSuccess)
-        e = launch_small_part<T, HERM, NBASE, false, kSmallRqTop>(single, sp, top_first,
-                                                                   single.t.n_ado, true, stream);
+        e = launch_small_part<T, HERM, NBASE, false, kSmallRqTop, kSmallElTop>(
+            single, sp, top_first, single.t.n_ado, true, stream);
     return e;
 }
 
