@@ -527,7 +527,7 @@ def main():
     warmup = args.warmup if args.warmup is not None else 5
     torch.cuda.set_device(0)
     h = heom.Hierarchy(prob, precision)
-    N, n = h.N, h.n_ado
+    N, n, W_modes = h.N, h.n_ado, h.W
     info = h.info
     rec_every = prob["record_every"]
     st = h.new_state(prob["rho0"])
@@ -608,11 +608,11 @@ def main():
         "hbm_GBps_algorithmic": hbm_gbs,
         "config": {
             "workload": "%s: %d sites, W=%d modes, depth %d, %d ADOs of %dx%d %s; RK4 dt=%g fs"
-                        % (args.workload, N, h.W, prob["depth"], n, N, N,
+                        % (args.workload, N, W_modes, prob["depth"], n, N, N,
                            {heom.FP32_MIXED: "complex64 (sigma_0 complex128)",
                             heom.FP32_HERM: "Hermitian-packed real float32 (sigma_0 complex128)",
                             heom.FP64: "complex128"}[precision], prob["dt_fs"]),
-            "n_ado": n, "n_states": N, "n_modes": h.W, "depth": prob["depth"],
+            "n_ado": n, "n_states": N, "n_modes": W_modes, "depth": prob["depth"],
             "precision": args.precision, "record_every": rec_every,
             "bytes_per_step_algorithmic": step_bytes,
         },
