@@ -2214,7 +2214,10 @@ static int small_tile(const Job& single, int tsize, bool plus, int rq, int el, s
     return GA;
 }
 
-constexpr int kSmallRqPlus = 4, kSmallRqTop = 2;
+// row slots per thread: the launch below the top level takes 8 when its
+// full tile needs more than 2 (W + D rows of N per ADO), else 2, whose
+// registers leave the row decode to the compiler
+constexpr int kSmallRqPlusWide = 8, kSmallRqPlusNarrow = 2, kSmallRqTop = 2;
 // elements per thread: the top-level launch takes two (twice the ADOs per
 // tile for the same per-tile overhead)
 constexpr int kSmallElPlus = 1, kSmallElTop = 2;
@@ -2229,14 +2232,22 @@ static size_t small_lds_budget(int per_cu) { return (size_t)(160 * 1024 / per_cu
 // 7 x 7: 9.5 against 20 us per stage).
 constexpr int kSmallMinAdos = 32768;
 
+static bool small_plus_wide(const Job& single) {
+    const int N = single.t.N, NN = N * N, Dm = std::max(single.t.D, 1);
+    int GA = std::max(1, 256 / NN);
+    const int cap = g_max_ados_per_tile.load();
+    if (cap > 0) GA = std::min(GA, cap);
+    return GA * (Dm + single.t.W) * N * (single.herm ? 1 : 2) > 256 * kSmallRqPlusNarrow;
+}
+
 static bool small_eligible(const Job& single, int tsize) {
     if (single.t.N > 16 || single.t.D < 1 || single.t.n_ado < kSmallMinAdos) return false;
     size_t l;
     const size_t bp = small_lds_budget(tsize == 4 ? small_waves<float, true>() : small_waves<double, true>());
     const size_t bt = small_lds_budget(tsize == 4 ? small_waves<float, false>() : small_waves<double, false>());
+    const int rq = small_plus_wide(single) ? kSmallRqPlusWide : kSmallRqPlusNarrow;
     return small_tile(single, tsize, false, kSmallRqTop, kSmallElTop, bt, &l) > 0 &&
-           (single.n_low == 0 ||
-            small_tile(single, tsize, true, kSmallRqPlus, kSmallElPlus, bp, &l) > 0);
+           (single.n_low == 0 || small_tile(single, tsize, true, rq, kSmallElPlus, bp, &l) > 0);
 }
 
 template <typename T, bool HERM, int NBASE, bool PLUS, int RQ, int EL>
@@ -2273,8 +2284,11 @@ static hipError_t launch_small_n(const Job& single, const StageSpec& sp, hipStre
     const int top_first = 1 + single.n_low;
     hipError_t e = hipSuccess;
     if (single.n_low > 0)
-        e = launch_small_part<T, HERM, NBASE, true, kSmallRqPlus, kSmallElPlus>(
-            single, sp, 1, top_first, false, stream);
+        e = small_plus_wide(single)
+                ? launch_small_part<T, HERM, NBASE, true, kSmallRqPlusWide, kSmallElPlus>(
+                      single, sp, 1, top_first, false, stream)
+                : launch_small_part<T, HERM, NBASE, true, kSmallRqPlusNarrow, kSmallElPlus>(
+                      single, sp, 1, top_first, false, stream);
     if (e == hipSuccess)
         e = launch_small_part<T, HERM, NBASE, false, kSmallRqTop, kSmallElTop>(
             single, sp, top_first, single.t.n_ado, true, stream);
