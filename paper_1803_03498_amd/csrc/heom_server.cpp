@@ -12,9 +12,10 @@
 // are copied to pinned host memory and their arena ranges are freed once the
 // copy has completed on the stream.
 //
-// Two kinds of request leave the batched launches.  A large FP32 population
-// run with 10 <= N <= 64 gets launches of its own on the persistent
-// matrix-core kernel (its ADOs fill the device).  An eligible dipole request
+// Two kinds of request leave the batched launches.  A large run gets
+// launches of its own on a persistent kernel (its ADOs fill the device):
+// FP32 Hermitian runs with 10 <= N <= 64 on the matrix-core one, runs with
+// N <= 16 and at least 32768 ADOs on the FMA one.  An eligible dipole request
 // (ground state uncoupled, initial states in the (e, g) column, at most three
 // directions) runs in the coherence-block form of heom_propagate_block: its
 // ADOs keep only their (e, g) column, the three directions side by side
@@ -47,8 +48,9 @@ namespace {
 constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 constexpr int kMaxRuns = 8;
 constexpr size_t kPinnedPool = size_t(256) << 20;
-// Population runs at least this large get launches of their own.
-constexpr int64_t kSoloMinAdos = 2048;
+// Runs at least this large get launches of their own (matrix-core and FMA
+// persistent kernels; the second matches the FMA kernel's own threshold).
+constexpr int64_t kSoloMinAdos = 2048, kSoloSmallMinAdos = 32768;
 
 // First-fit allocator of 256-byte-aligned ranges of [0, size).
 class RangeAllocator {
@@ -141,10 +143,15 @@ size_t job_table_bytes(size_t jobs_cap, int max_active) {
     return align256(jobs_cap * sizeof(heom::Job)) + align256((size_t)max_active * sizeof(heom::BlockJob));
 }
 
-// A full-form job with launches of its own (persistent kernel).
+// A full-form job with launches of its own: FP32 Hermitian runs with
+// 10 <= N <= 64 and at least kSoloMinAdos ADOs (the persistent matrix-core
+// kernel), and runs with N <= 16 and at least kSoloSmallMinAdos ADOs in
+// either precision (the persistent FMA kernel).
 bool solo_job(int precision, const heom::Job& j) {
-    return precision == HEOM_FP32_MIXED && j.herm && j.t.N >= 10 && j.t.N <= 64 &&
-           j.t.h_complex == 0 && j.t.n_ado >= kSoloMinAdos;
+    if (precision == HEOM_FP32_MIXED && j.herm && j.t.N >= 10 && j.t.N <= 64 &&
+        j.t.h_complex == 0)
+        return j.t.n_ado >= kSoloMinAdos;
+    return j.t.N <= 16 && j.t.n_ado >= kSoloSmallMinAdos;
 }
 
 struct Group {

@@ -269,3 +269,31 @@ def test_matrix_core_sizes_in_the_mix(heom, orc, precision):
             # which the oracle would take a minute for)
             _, rec_ref = orc.run(r[0])
             assert np.max(np.abs(res["records"][0] - rec_ref)) <= 1e-12, s
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_persistent_fma_requests_in_the_mix(heom, precision):
+    # runs with N <= 16 and at least 32768 ADOs get launches of their own on
+    # the persistent FMA kernel (the 74613- and 38760-ADO runs here) beside
+    # batched small requests: mix and alone bit for bit, heom_propagate
+    # within the precision's tolerance
+    specs = [(81, 8, 6, 1), (82, 7, 6, 1), (83, 5, 3, 1), (84, 4, 2, 0)]
+    reqs = []
+    for s in specs:
+        r = _population(*s, n_steps=12)
+        r[0]["dt_fs"] = 0.5
+        reqs.append(r)
+    srv = heom.Server(ARENA, max_active=8)
+    tickets = [srv.submit(r, precision) for r in reqs]
+    results = [srv.wait(t, 120.0) for t in tickets]
+    srv.close()
+    tol = 1e-12 if precision == 0 else 1e-5
+    for s, r, res in zip(specs, reqs, results):
+        _case("persistent FMA mix", precision, s)
+        assert res["status"] == 0
+        one = heom.Server(ARENA, max_active=1)
+        alone = one.wait(one.submit(r, precision), 120.0)
+        one.close()
+        assert np.array_equal(res["records"], alone["records"]), s
+        ref = _alone(heom, r, precision)
+        assert np.max(np.abs(res["records"] - ref)) <= tol, s
