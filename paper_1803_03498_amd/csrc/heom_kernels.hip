@@ -646,16 +646,16 @@ __device__ __forceinline__ void fma_rhs(const FmaTile<T>& V, const NbSrc<T>& nbs
 }
 
 // --------------------------------------------------------------------------
-// Bulk stage kernel, wavefront-FMA path (N < 16, or complex H): a workgroup
-// of fma_block threads takes GA = max(1, fma_block / N^2) consecutive ADOs
-// (computed per job by the host; a batched launch uses the block size of its
-// largest N, and the element loops stride by the launch's block size);
-// every thread owns whole matrix elements.  Each ADO's link rows (the
-// compact "-" list with its states and weights, the "+" neighbours and
-// weights) are copied to LDS first from the precomputed tables, so an
-// element's coupling lines need one global load per contributing neighbour.
-// The kernel is kept lean in registers: at this size the number of resident
-// workgroups, not the order of the loads, decides the throughput.
+// Bulk stage kernel, wavefront-FMA path (batched launches with N < 16 or a
+// complex H, and single propagations below the persistent FMA kernel's
+// size): a workgroup of fma_block threads takes GA = max(1, fma_block / N^2)
+// consecutive ADOs (computed per job by the host; a batched launch uses the
+// block size of its largest N, and the element loops stride by the launch's
+// block size); every thread owns whole matrix elements.  Each ADO's link
+// rows (the compact "-" list with its states and weights, the "+"
+// neighbours and weights) are copied to LDS first from the precomputed
+// tables; an element's coupling lines then gather one element per
+// contributing neighbour (fma_rhs).
 // HC: some job of the launch has a complex H (otherwise H is real).
 // --------------------------------------------------------------------------
 template <typename T, bool BATCHED, bool HC>
@@ -2131,11 +2131,13 @@ static hipError_t launch_persist_nb(const Job& single, int total_tiles, const St
                                : launch_persist_vec<NB, 1>(single, total_tiles, sp, stream);
 }
 
-// The persistent kernel takes single-job FP32 stages over Hermitian ADOs
-// with a real H and 10 <= N <= 64.  Below N = 10 an ADO fills too little of
-// a 16 x 16 matrix-core tile, and the FMA kernel's tiles of several ADOs are
-// faster (measured at N = 7: 15.9 against 17.8 ms per launch on the 12.3M-ADO
-// (6, 6) FMO reference; at N = 14, 1.18 against 0.40 ms on 237k ADOs).
+// The persistent matrix-core kernel takes single-job FP32 stages over
+// Hermitian ADOs with a real H and 10 <= N <= 64.  Below N = 10 an ADO fills
+// too little of a 16 x 16 matrix-core tile, and tiles of several ADOs on the
+// FMA path are faster (the 12.3M-ADO (6, 6) FMO reference at N = 7: 17.8 ms
+// per stage here, 15.9 ms on the one-launch FMA kernel, 8.4 ms on the
+// persistent FMA kernel; at N = 14, 237k ADOs: 0.39 ms here against 1.18 ms
+// on the one-launch FMA kernel).
 static int persist_blocks(const Job& single, bool batched) {
     if (batched || single.herm == 0 || single.t.h_complex != 0 || single.t.N < 10 ||
         single.t.N > 64)
