@@ -539,13 +539,19 @@ def main():
     lib = heom.load()
     h.propagate(st, prob["dt_fs"], warmup, rec_every, hermitian=True, work=work)
     torch.cuda.synchronize()
-    lib.heom_timing_enable(1)
-    lib.heom_timing_read(None, None, None, 1)
-    torch.cuda.synchronize()
+    # the timed steps as a caller runs them (step graph replays for runs of
+    # 8 steps or more): the line's value
     t0 = time.perf_counter()
     rec = h.propagate(st, prob["dt_fs"], steps, rec_every, hermitian=True, work=work)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # the same number of steps again with HIP events around every bulk
+    # launch (direct launches): the roofline's per-launch time
+    lib.heom_timing_enable(1)
+    lib.heom_timing_read(None, None, None, 1)
+    torch.cuda.synchronize()
+    h.propagate(st, prob["dt_fs"], steps, rec_every, hermitian=True, work=work)
+    torch.cuda.synchronize()
     lib.heom_timing_enable(0)
     ms = ctypes.c_double()
     launches = ctypes.c_int64()

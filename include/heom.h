@@ -215,7 +215,10 @@ heom_status heom_rhs(const heom_hierarchy* h, heom_state in, heom_state out, int
  * Synchronous: returns after the stream has finished; if host_out != NULL
  * the records are copied to host_out [n_rec][heom_record_doubles].
  * HEOM_E_UNSTABLE if dt exceeds the RK4 bound for the problem's rates;
- * HEOM_E_NUMERIC if a recorded observable was not finite. */
+ * HEOM_E_NUMERIC if a recorded observable was not finite.  Runs of 8 steps
+ * or more launch the first step directly and replay a HIP graph of one step
+ * (captured on a private stream) for the rest, unless kernel timing is on
+ * (heom_timing_enable); the results are the same either way, bit for bit. */
 heom_status heom_propagate(const heom_hierarchy* h, heom_state io, void* work_dev,
                            size_t work_bytes, double dt_fs, int64_t n_steps, int32_t record_every,
                            const heom_observable* obs, int32_t hermitian, double* host_out,

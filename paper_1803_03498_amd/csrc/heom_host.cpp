@@ -758,12 +758,54 @@ heom_status heom_rhs(const heom_hierarchy* h, heom_state in, heom_state out, int
 
 namespace {
 
+// Steps from which heom_propagate replays a captured step graph.
+constexpr int64_t kGraphMinSteps = 8;
+
+// One RK4 step's launches captured on a private stream and instantiated; the
+// destructor waits for the caller's stream before the graph goes away.
+struct StepGraph {
+    hipStream_t caller;
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    explicit StepGraph(hipStream_t s) : caller(s) {}
+    template <class F>
+    bool capture(F&& launch) {
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+            cs = nullptr;
+            return false;
+        }
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+        const hipError_t le = launch(cs);
+        const hipError_t ee = hipStreamEndCapture(cs, &graph);
+        if (le != hipSuccess || ee != hipSuccess || !graph) {
+            (void)hipGetLastError();
+            return false;
+        }
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            exec = nullptr;
+            (void)hipGetLastError();
+            return false;
+        }
+        return true;
+    }
+    ~StepGraph() {
+        if (exec) {
+            (void)hipStreamSynchronize(caller);
+            (void)hipGraphExecDestroy(exec);
+        }
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+};
+
 // heom_propagate on a given workspace.  `timing` allows the benchmark event
-// timing (which creates HIP events); the no-alloc entry point passes false.
+// timing (which creates HIP events) and `graphs` the step graph (which
+// allocates); the no-alloc entry point passes false for both.
 heom_status propagate_impl(const heom_hierarchy* h, heom_state io, void* work_dev,
                            size_t work_bytes, double dt_fs, int64_t n_steps, int32_t record_every,
                            const heom_observable* obs, int32_t hermitian, double* host_out,
-                           void* stream, bool timing) {
+                           void* stream, bool timing, bool graphs) {
     if (!h) return fail(HEOM_E_INVAL, "hierarchy is NULL");
     heom_status s;
     if ((s = check_state(h, io, "io")) != HEOM_OK) return s;
@@ -819,15 +861,40 @@ heom_status propagate_impl(const heom_hierarchy* h, heom_state io, void* work_de
         for (auto& x : ev) HIP_TRY(hipEventCreate(&x));
     }
     static const int kPasses[4] = {2, 3, 3, 5};
-    for (int64_t step = 0; step < n_steps; ++step) {
+    auto launch_step = [&](int64_t step, hipStream_t s) -> hipError_t {
         for (int k = 0; k < 4; ++k) {
-            hipError_t e = heom::launch_stage(j, nullptr, 0, tiles, h->d.precision, sp[k], st,
+            hipError_t e = heom::launch_stage(j, nullptr, 0, tiles, h->d.precision, sp[k], s,
                                               timed ? ev[2 * (step * 4 + k)] : nullptr,
                                               timed ? ev[2 * (step * 4 + k) + 1] : nullptr);
-            if (e != hipSuccess)
-                return fail(HEOM_E_DEVICE, "stage launch (%s): %s", heom::last_launch_failure(),
-                            hipGetErrorString(e));
+            if (e != hipSuccess) return e;
         }
+        return hipSuccess;
+    };
+    // Small hierarchies are bound by launch latency: after one step launched
+    // directly (which also sets the kernels' attributes up), the four stage
+    // launches of a step are captured once in a HIP graph and the graph is
+    // replayed for the remaining steps.  The kernels keep the step count on
+    // the device, so every replay is the same launch.  A capture that fails
+    // falls back to direct launches.
+    StepGraph graph(st);
+    int64_t step = 0;
+    if (graphs && !timed && tiles > 0 && n_steps >= kGraphMinSteps) {
+        hipError_t e = launch_step(0, st);
+        if (e != hipSuccess)
+            return fail(HEOM_E_DEVICE, "stage launch (%s): %s", heom::last_launch_failure(),
+                        hipGetErrorString(e));
+        step = 1;
+        if (graph.capture([&](hipStream_t cs) { return launch_step(1, cs); })) {
+            for (; step < n_steps; ++step)
+                if ((e = hipGraphLaunch(graph.exec, st)) != hipSuccess)
+                    return fail(HEOM_E_DEVICE, "graph launch: %s", hipGetErrorString(e));
+        }
+    }
+    for (; step < n_steps; ++step) {
+        hipError_t e = launch_step(step, st);
+        if (e != hipSuccess)
+            return fail(HEOM_E_DEVICE, "stage launch (%s): %s", heom::last_launch_failure(),
+                        hipGetErrorString(e));
     }
     if (n_steps == 0) {
         // record the initial state only: a stage-1 pass into slot 1 does it
@@ -868,7 +935,7 @@ heom_status heom_propagate(const heom_hierarchy* h, heom_state io, void* work_de
                            const heom_observable* obs, int32_t hermitian, double* host_out,
                            void* stream) {
     return propagate_impl(h, io, work_dev, work_bytes, dt_fs, n_steps, record_every, obs,
-                          hermitian, host_out, stream, true);
+                          hermitian, host_out, stream, true, true);
 }
 
 heom_status heom_propagate_noalloc(const heom_hierarchy* h, heom_state io, double dt_fs,
@@ -892,7 +959,7 @@ heom_status heom_propagate_noalloc(const heom_hierarchy* h, heom_state io, doubl
     if (e != hipSuccess)
         return fail(HEOM_E_DEVICE, "static scratch lookup: %s", hipGetErrorString(e));
     return propagate_impl(h, io, scratch, scratch_bytes, dt_fs, n_steps, record_every, obs,
-                          hermitian, host_out, stream, false);
+                          hermitian, host_out, stream, false, false);
 }
 
 heom_status heom_set_launch_shape(int32_t max_workgroups, int32_t max_ados_per_tile) {
