@@ -394,6 +394,13 @@ heom_status heom_wait(heom_server* s, uint64_t ticket, double timeout_s, heom_re
 heom_status heom_cancel(heom_server* s, uint64_t ticket);
 /* Thread-safe: free the result of a finished request. */
 heom_status heom_release(heom_server* s, uint64_t ticket);
+/* Thread-safe: append one JSON object per finished request, one per line,
+ * to the file at `path` (created if absent); NULL stops the log.  Fields:
+ * ticket, status, form ("full" / "block"), runs, n_states, n_ado, n_steps,
+ * queue_ms (admission - submission), service_ms (finish - admission),
+ * latency_ms, ado_updates (n_ado * n_steps * runs).  HEOM_E_INVAL if the
+ * file cannot be opened. */
+heom_status heom_server_set_log(heom_server* s, const char* path);
 /* Stop the scheduler (running requests are cancelled) and free the server. */
 heom_status heom_server_destroy(heom_server* s);
 

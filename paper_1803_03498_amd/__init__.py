@@ -396,6 +396,11 @@ class Server:
         check(load().heom_release(self.handle, ticket))
         self._keep.pop(ticket, None)
 
+    def set_log(self, path):
+        """heom_server_set_log: one JSON line per finished request appended to
+        `path` (None stops the log)."""
+        check(load().heom_server_set_log(self.handle, None if path is None else str(path).encode()))
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             load().heom_server_destroy(self.handle)

@@ -107,6 +107,7 @@ SIGNATURES = {
     "heom_cancel": (i32, [vp, u64]),
     "heom_release": (i32, [vp, u64]),
     "heom_server_destroy": (i32, [vp]),
+    "heom_server_set_log": (i32, [vp, ctypes.c_char_p]),
 }
 
 _lib = None

@@ -30,6 +30,7 @@
 
 #include <algorithm>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -194,6 +195,7 @@ struct heom_server {
     std::vector<Group> groups;
     bool dirty = false;
     std::thread thr;
+    std::FILE* log = nullptr;  // per-request JSON lines (heom_server_set_log)
 
     void run();
     void admit();
@@ -221,6 +223,20 @@ void heom_server::finish(Req* r, heom_status st) {
     r->status = st;
     r->phase = Req::DONE;
     r->t_finish = heom::monotonic_seconds();
+    if (log) {
+        const bool admitted = r->t_admit > 0.0;
+        const double t_admit = admitted ? r->t_admit : r->t_finish;
+        std::fprintf(log,
+                     "{\"ticket\": %llu, \"status\": %d, \"form\": \"%s\", \"runs\": %d, "
+                     "\"n_states\": %d, \"n_ado\": %lld, \"n_steps\": %lld, \"queue_ms\": %.3f, "
+                     "\"service_ms\": %.3f, \"latency_ms\": %.3f, \"ado_updates\": %lld}\n",
+                     (unsigned long long)r->ticket, (int)st, r->block ? "block" : "full", r->n_runs,
+                     r->info.n_states, (long long)r->info.n_ado, (long long)r->n_steps,
+                     1e3 * (t_admit - r->t_submit), 1e3 * (r->t_finish - t_admit),
+                     1e3 * (r->t_finish - r->t_submit),
+                     (long long)(r->info.n_ado * r->n_steps * r->n_runs));
+        std::fflush(log);
+    }
     cv_done.notify_all();
 }
 
@@ -864,6 +880,16 @@ heom_status heom_release(heom_server* s, uint64_t ticket) {
     return HEOM_OK;
 }
 
+heom_status heom_server_set_log(heom_server* s, const char* path) {
+    if (!s) return srv_fail(HEOM_E_INVAL, "server is NULL");
+    std::FILE* f = nullptr;
+    if (path && !(f = std::fopen(path, "a"))) return srv_fail(HEOM_E_INVAL, "cannot open the log file");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->log) std::fclose(s->log);
+    s->log = f;
+    return HEOM_OK;
+}
+
 heom_status heom_server_destroy(heom_server* s) {
     if (!s) return HEOM_OK;
     {
@@ -882,6 +908,7 @@ heom_status heom_server_destroy(heom_server* s) {
     if (s->stage_ev) (void)hipEventDestroy(s->stage_ev);
     for (auto& e : s->step_ev)
         if (e) (void)hipEventDestroy(e);
+    if (s->log) std::fclose(s->log);
     delete s;
     return HEOM_OK;
 }

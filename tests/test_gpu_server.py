@@ -297,3 +297,27 @@ def test_persistent_fma_requests_in_the_mix(heom, precision):
         assert np.array_equal(res["records"], alone["records"]), s
         ref = _alone(heom, r, precision)
         assert np.max(np.abs(res["records"] - ref)) <= tol, s
+
+
+def test_request_log(heom, tmp_path):
+    # one JSON line per finished request, with the form, sizes and timings
+    import json
+    path = tmp_path / "requests.jsonl"
+    runs_b = _absorption(41, 4, 3, 1, n_steps=30)
+    runs_f = _population(42, 5, 3, 1, n_steps=30)
+    srv = heom.Server(ARENA, max_active=4)
+    srv.set_log(path)
+    tb, tf = srv.submit(runs_b, heom.FP32_MIXED), srv.submit(runs_f, heom.FP32_MIXED)
+    rb, rf = srv.wait(tb, 120.0), srv.wait(tf, 120.0)
+    srv.set_log(None)
+    srv.close()
+    lines = [json.loads(x) for x in path.read_text().splitlines()]
+    by = {x["ticket"]: x for x in lines}
+    assert set(by) == {tb, tf}
+    assert by[tb]["form"] == "block" and by[tf]["form"] == "full"
+    assert by[tb]["runs"] == 3 and by[tf]["runs"] == 1 and by[tf]["n_states"] == 5
+    for t, res in ((tb, rb), (tf, rf)):
+        x = by[t]
+        assert x["status"] == 0 and x["n_steps"] == 30
+        assert abs(x["latency_ms"] - 1e3 * (res["t_finish"] - res["t_submit"])) < 1e-2
+        assert abs(x["queue_ms"] + x["service_ms"] - x["latency_ms"]) < 1e-2
