@@ -111,6 +111,8 @@ def parse():
                     help="time the serving replays may take (0 skips the serving leg)")
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-arena-gb", type=float, default=48.0)
+    ap.add_argument("--serve-cpu-requests", type=int, default=128,
+                    help="requests of the mix timed on the oracle (the first ones)")
     ap.add_argument("--serve-log", default=None,
                     help="write one JSON line per served request to this file")
     return ap.parse_args()
@@ -176,6 +178,21 @@ def _bulk_kernel_name(info, precision, N, heom):
     return "k_bulk_mfma_pk" if precision == heom.FP32_HERM else "k_bulk_mfma"
 
 
+def _table_bytes_per_launch(kernel, n, W, D, fp64):
+    """Bytes of link tables and coefficients that one stage launch reads for
+    the ADOs u >= 1, outside the algorithmic bytes: per ADO its "-" links
+    (neighbour and mode, state, the two weights) and its damping rate, and
+    per ADO below the top level its "+" links (neighbour, weight); the
+    FP64-coefficient kernels read the weights in FP64, the level-major FP64
+    matrix-core kernel also the level byte."""
+    from math import comb
+    Dm = max(D, 1)
+    n_low = comb(W + D - 1, W) - 1 if D >= 1 and W >= 1 else 0
+    w_bytes = 16 if fp64 else 8
+    per_ado = Dm * (8 + 4 + w_bytes) + 8 + (1 if kernel == "k_bulk_mfma" else 0)
+    return float((n - 1) * per_ado + n_low * W * (4 + 8))
+
+
 def _fp64_reference(heom, torch, lib, prob, precision, steps, rec_every, N, n):
     """The benchmarked steps from the initial state in FP64 (timed, with its
     bulk-kernel events) and in `precision`; returns the FP64 figures and the
@@ -212,6 +229,11 @@ def _fp64_reference(heom, torch, lib, prob, precision, steps, rec_every, N, n):
     a, b = recs[heom.FP64], recs[precision]
     out["fp32_vs_fp64_max_population_error"] = float(np.max(np.abs(a[:, :N] - b[:, :N])))
     out["fp32_trace_drift"] = float(np.max(np.abs(b[:, N] - 1.0)))
+    # max |sigma_0 - sigma_0^+| over the records (column N + 2 of a
+    # population record)
+    out["fp32_hermiticity_residual"] = float(np.max(b[:, N + 2]))
+    out["fp64_hermiticity_residual"] = float(np.max(a[:, N + 2]))
+    out["fp64_trace_drift"] = float(np.max(np.abs(a[:, N] - 1.0)))
     out["records_compared"] = int(a.shape[0])
     return out
 
@@ -227,11 +249,12 @@ def _percentile(xs, q):
 
 
 def _replay(heom, reqs, precision, max_active, arena_bytes, rate, form=0, timeout_s=900.0,
-            log=None, tag=""):
+            log=None, tag="", keep=None):
     """Submit requests at their (scaled) Poisson arrival times (all at once
     when rate is None); returns per-request latencies (s), the makespan (s),
     the ADO-updates done, the number of requests run in the coherence-block
-    form and each request's service time (finish - admission, s)."""
+    form and each request's service time (finish - admission, s).  keep: a
+    dict that receives each request's records by request id."""
     srv = heom.Server(arena_bytes, max_active)
     t0 = time.monotonic()
     arrival = 0.0
@@ -255,6 +278,8 @@ def _replay(heom, reqs, precision, max_active, arena_bytes, rate, form=0, timeou
         ado_updates = r["n_ado"] * r["runs"][0]["n_steps"] * len(r["runs"])
         work += ado_updates
         n_block += res["form"] == 2
+        if keep is not None:
+            keep[r["id"]] = res["records"]
         if log is not None:
             log.write(json.dumps({
                 "replay": tag, "request": r["id"], "kind": r["kind"], "N": r["N"],
@@ -282,7 +307,122 @@ def _serve_stats(lat, span, work, n):
             "makespan_s": span}
 
 
-def serve_leg(args):
+def _oracle_request_seconds(task):
+    """CPU seconds of the FP64 oracle for one whole request on this core:
+    per run, its model setup plus n_steps RK4 steps (the runs of a request
+    differ only in their initial state and dipole).  The step is the
+    oracle's own step code timed on every stride-th ADO (all of them when
+    that fits `budget`), scaled to all ADOs; the smaller of two timings.
+    Returns (seconds, stride)."""
+    runs, n_steps, budget = task
+    import oracle
+    p = runs[0]
+    N = np.asarray(p["H"]).shape[0]
+    _, n = oracle.sizes(p)
+    x = np.zeros((n, N, N), np.complex128)  # pages are touched only where read
+    x[0] = p["rho0"]
+    t_setup = float("inf")
+    for _ in range(2):  # model and table construction only (each call builds them)
+        t0 = time.perf_counter()
+        oracle.rhs(p, x, 0, 0)
+        t_setup = min(t_setup, time.perf_counter() - t0)
+    stride = max(1, n // 256)
+    while True:
+        sec = oracle.time_step_sample(p, x, p["dt_fs"], 0, n, stride, 2)
+        if stride == 1 or sec > 0.1 * budget:
+            break
+        stride = max(1, stride // 8)
+    step = sec * stride * n / (n + stride - 1 - (n - 1) % stride)  # per sampled ADO x n
+    return len(runs) * (t_setup + step * n_steps), stride
+
+
+def serve_cpu_oracle(mix, n_steps, target_s):
+    """The FP64 oracle on every host core as independent processes, one
+    request at a time each, over the whole mix: each request's CPU time is
+    measured on a bounded sample (see _oracle_request_seconds) while all
+    processes run, so memory contention is included.  Runs before the GPU is
+    touched (its worker processes are spawned)."""
+    import multiprocessing as mp
+    procs = max(1, min(16, len(os.sched_getaffinity(0))))
+    budget = min(3.0, max(0.05, target_s * procs / max(len(mix), 1)))
+    # largest first (an ADO costs about N^3), so that the longest single
+    # steps do not come last
+    cost = [r["n_ado_est"] * r["N"] ** 3 for r in mix]
+    order = sorted(range(len(mix)), key=lambda i: -cost[i])
+    tasks = [(mix[i]["runs"], n_steps, budget) for i in order]
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(procs) as pool:
+        res = pool.map(_oracle_request_seconds, tasks, chunksize=1)
+    wall = time.perf_counter() - t0
+    secs, steps = [0.0] * len(mix), [0] * len(mix)
+    for i, (sec, st) in zip(order, res):
+        secs[i], steps[i] = sec, st
+    return {"seconds": secs, "steps_timed": steps, "procs": procs, "budget_s": budget,
+            "wall_s": wall}
+
+
+def _serve_cpu_baseline(cpu, n):
+    """Requests/s of the oracle on cpu["procs"] cores for the first n
+    requests (each core runs whole requests one after another)."""
+    n = min(n, len(cpu["seconds"]))
+    secs = cpu["seconds"][:n]
+    mean = sum(secs) / max(len(secs), 1)
+    sampled = sum(1 for s in cpu["steps_timed"][:n] if s > 1)
+    return {"value": cpu["procs"] / mean, "unit": "req/s", "cores": cpu["procs"],
+            "kind": "oracle", "cpu_model": _cpu_model(),
+            "p50_request_s_one_core": _percentile(secs, 50),
+            "p99_request_s_one_core": _percentile(secs, 99),
+            "sample": "FP64 oracle on %d host cores as independent processes, one request each "
+                      "at a time, over the first %d requests of the mix: each request's RK4 "
+                      "step timed with the oracle's step code over all its ADOs (%d requests) "
+                      "or every k-th ADO (%d, k chosen so the sample takes about %.2f s) and "
+                      "scaled to all ADOs, its steps and runs, plus its model setup per run; "
+                      "%.0f s wall for the sample"
+                      % (cpu["procs"], n, n - sampled, sampled, 0.1 * cpu["budget_s"],
+                         cpu["wall_s"])}
+
+
+def _serve_accuracy(heom, reqs, got, ref):
+    """Errors of the batched FP32-mixed results against the plain FP64 ones
+    (the FP64 path, itself held to the oracle at 1e-12 by the parity
+    tests) over the same requests: population error, trace drift and
+    Hermiticity residual of the population requests, and for the absorption
+    requests the dipole-response error and the spectrum error (trapezoid DFT
+    over 1 ps on the -1000..1000 cm^-1 grid, max |S - S_ref| / max |S_ref|)."""
+    w = np.arange(-1000.0, 1001.0, 1.0)
+    out = {"requests_compared": 0, "population_requests": 0, "absorption_requests": 0,
+           "max_population_error": 0.0, "max_trace_drift": 0.0,
+           "max_hermiticity_residual": 0.0, "max_dipole_response_error": 0.0,
+           "max_spectrum_rel_error": 0.0}
+    for r in reqs:
+        a, b = got.get(r["id"]), ref.get(r["id"])
+        if a is None or b is None:
+            continue
+        out["requests_compared"] += 1
+        dt = r["runs"][0]["dt_fs"] * r["runs"][0]["record_every"]
+        if r["kind"] == "population":
+            N = np.asarray(r["runs"][0]["H"]).shape[0]
+            out["population_requests"] += 1
+            out["max_population_error"] = max(out["max_population_error"],
+                                               float(np.max(np.abs(a[..., :N] - b[..., :N]))))
+            out["max_trace_drift"] = max(out["max_trace_drift"],
+                                         float(np.max(np.abs(a[..., N] - 1.0))))
+            out["max_hermiticity_residual"] = max(out["max_hermiticity_residual"],
+                                                  float(np.max(a[..., N + 2])))
+        else:
+            out["absorption_requests"] += 1
+            Pa = a[:, :, 0] + 1j * a[:, :, 1]
+            Pb = b[:, :, 0] + 1j * b[:, :, 1]
+            out["max_dipole_response_error"] = max(out["max_dipole_response_error"],
+                                                   float(np.max(np.abs(Pa - Pb))))
+            Sa, Sb = heom.spectrum(Pa, dt, w), heom.spectrum(Pb, dt, w)
+            out["max_spectrum_rel_error"] = max(
+                out["max_spectrum_rel_error"],
+                float(np.max(np.abs(Sa - Sb)) / max(np.max(np.abs(Sb)), 1e-300)))
+    return out
+
+
+def serve_leg(args, cpu=None):
     """Serving mix (seed 512): continuous batching in FP32-mixed, with the
     coherence-block form for absorption requests, against plain FP64
     one-solve-at-a-time on full matrices, on the same Poisson traces at
@@ -345,11 +485,16 @@ def serve_leg(args):
         rate = x * capacity
         print("serve: replay at %.1fx capacity (%.2f req/s): batched" % (x, rate),
               file=sys.stderr, flush=True)
+        # the results of the headline load are kept for their errors
+        kb, kf = ({}, {}) if x == 0.8 else (None, None)
         lat_b, span_b, work_b, _, _ = _replay(heom, reqs, heom.FP32_MIXED, slots, arena, rate,
-                                              log=log, tag="batched_%.1fx" % x)
+                                              log=log, tag="batched_%.1fx" % x, keep=kb)
         print("serve: replay at %.1fx capacity: plain FP64" % x, file=sys.stderr, flush=True)
         lat_f, span_f, work_f, _, _ = _replay(heom, reqs, heom.FP64, 1, arena, rate, form=1,
-                                              log=log, tag="plain_fp64_%.1fx" % x)
+                                              log=log, tag="plain_fp64_%.1fx" % x, keep=kf)
+        if kb is not None:
+            out["accuracy_vs_fp64"] = _serve_accuracy(heom, reqs, kb, kf)
+            del kb, kf
         b, f = _serve_stats(lat_b, span_b, work_b, n), _serve_stats(lat_f, span_f, work_f, n)
         out["replays"].append({
             "load": x, "arrival_rate_req_per_s": rate,
@@ -362,6 +507,8 @@ def serve_leg(args):
               flush=True)
     if log is not None:
         log.close()
+    if cpu is not None:
+        out["cpu_baseline"] = _serve_cpu_baseline(cpu, n)
     out["workload"] = ("serving mix: the first %d of %d requests (seed 512), N in 2..14, D in 2..5, "
                        "M in 0..1, population or 3-direction absorption, %d RK4 steps of 1 fs; "
                        "Poisson arrivals at 0.5x, 0.8x, 1.0x of the batched closed-loop capacity"
@@ -369,9 +516,27 @@ def serve_leg(args):
     return out
 
 
+def _mix_cpu_oracle(args):
+    """The oracle leg of the serving mix (before any GPU work), or None."""
+    if args.cpu_baseline_seconds <= 0 or args.serve_seconds <= 0:
+        return None
+    mix = hi.serving_mix(n_requests=args.serve_requests, seed=512, n_steps=args.serve_steps)
+    mix = mix[:max(1, args.serve_cpu_requests)]
+    from math import comb
+    for r in mix:
+        W = sum(b["matsubara"] + 1 for b in r["runs"][0]["baths"])
+        r["n_ado_est"] = comb(W + r["depth"], W) * len(r["runs"])
+    print("serve: FP64 oracle on the host cores (%d requests)" % len(mix), file=sys.stderr,
+          flush=True)
+    cpu = serve_cpu_oracle(mix, args.serve_steps, args.cpu_baseline_seconds * 2)
+    print("serve: oracle leg %.0f s on %d processes" % (cpu["wall_s"], cpu["procs"]),
+          file=sys.stderr, flush=True)
+    return cpu
+
+
 def run_serve(args):
     """The serving leg on its own, as one JSON line."""
-    sv = serve_leg(args)
+    sv = serve_leg(args, _mix_cpu_oracle(args))
     r1 = sv["replays"][-1]["batched_fp32"]
     line = {
         "metric": METRIC,
@@ -390,7 +555,7 @@ def run_serve(args):
                    "arena_GB": args.serve_arena_gb},
         "serve": sv,
         "roofline": None,
-        "cpu_baseline": None,
+        "cpu_baseline": sv.get("cpu_baseline"),
     }
     print(json.dumps(line), flush=True)
 
@@ -514,6 +679,8 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    # the serving mix's oracle leg spawns its host processes before any GPU work
+    mix_cpu = _mix_cpu_oracle(args)
     import torch
 
     import paper_1803_03498_amd as heom
@@ -596,7 +763,7 @@ def main():
     if args.serve_seconds > 0:
         work = st = h = None  # the 48-site state and stage copies leave the device
         torch.cuda.empty_cache()
-        serve = serve_leg(args)
+        serve = serve_leg(args, mix_cpu)
 
     line = {
         "metric": METRIC,
@@ -632,6 +799,8 @@ def main():
             "traffic": traffic,
             "avg_launch_ms": avg_launch_s * 1e3,
             "bytes_per_launch_algorithmic": bytes_per_launch,
+            "table_bytes_per_launch": _table_bytes_per_launch(
+                kernel_short, n, W_modes, prob["depth"], precision == heom.FP64),
         },
         "cpu_baseline": cpu,
         "fp64": fp64,

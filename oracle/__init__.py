@@ -70,6 +70,8 @@ def lib():
         L.orc_pade_poles.argtypes = [i32, P(d), P(d)]
         L.orc_model_sizes.argtypes = [P(_Problem), P(i32), P(i64)]
         L.orc_rhs.argtypes = [P(_Problem), ctypes.c_void_p, ctypes.c_void_p, i64, i64]
+        L.orc_time_step_sample.argtypes = [P(_Problem), ctypes.c_void_p, d, i64, i64, i64, i32,
+                                           P(d)]
         L.orc_propagate.argtypes = [P(_Problem), ctypes.c_void_p, d, i64, i32, i32,
                                     ctypes.c_void_p, i32, ctypes.c_void_p]
         L.orc_spectrum.argtypes = [ctypes.c_void_p, i32, i64, d, ctypes.c_void_p, i64,
@@ -167,6 +169,19 @@ def rhs(prob, state, u_begin=0, u_end=-1):
     if lib().orc_rhs(ctypes.byref(pk.s), x.ctypes.data, out.ctypes.data, u_begin, u_end):
         raise ValueError("invalid problem")
     return out
+
+
+def time_step_sample(prob, state, dt_fs, u_begin=0, u_end=-1, stride=1, repeats=1):
+    """Seconds of one RK4 step's work for the ADOs u_begin, u_begin + stride,
+    ... below u_end, the smallest of `repeats` timings (timing only: the
+    model is built outside the timed region; see orc_time_step_sample)."""
+    pk = _Packed(prob)
+    x = np.ascontiguousarray(state, dtype=np.complex128)
+    sec = ctypes.c_double()
+    if lib().orc_time_step_sample(ctypes.byref(pk.s), x.ctypes.data, float(dt_fs), int(u_begin),
+                                  int(u_end), int(stride), int(repeats), ctypes.byref(sec)):
+        raise ValueError("invalid problem or out of memory")
+    return sec.value
 
 
 def record_size(N, kind):

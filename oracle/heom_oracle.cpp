@@ -26,9 +26,11 @@
 // Parity pins for every function live in tests/ (marker "not gpu").
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <vector>
@@ -538,6 +540,58 @@ int orc_propagate(const orc_problem* p, double* state, double dt_fs, int64_t n_s
         if (records && (step + 1) % record_every == 0)
             record(m, y, obs_kind, mu, ground, records + (r++) * rs);
     }
+    return 0;
+}
+
+// Timing only (for the CPU baseline): the work that one orc_propagate step
+// does for the ADOs u_begin, u_begin + stride, ... below u_end -- their four
+// evaluations and their share of the vector updates, with the same code --
+// timed on a steady clock after the model is built (table construction stays
+// out of the figure); the smallest of `repeats` timings goes to *seconds.
+// Neighbours that are not sampled are read as zeros (the stage arrays are
+// calloc'ed and only the sampled ADOs are written); `state` is not changed.
+int orc_time_step_sample(const orc_problem* p, const double* state, double dt_fs,
+                         int64_t u_begin, int64_t u_end, int64_t stride, int32_t repeats,
+                         double* seconds) {
+    Model m;
+    if (build_model(p, m) || !seconds || stride < 1 || repeats < 1) return -1;
+    const int64_t n_ado = (int64_t)m.tuples.size();
+    if (u_end < 0 || u_end > n_ado) u_end = n_ado;
+    if (u_begin < 0) u_begin = 0;
+    if (u_begin > u_end) return -1;
+    const size_t NN = (size_t)m.N * m.N, n = (size_t)n_ado * NN;
+    const cplx* y = reinterpret_cast<const cplx*>(state);
+    cplx* buf[5];
+    for (int b = 0; b < 5; ++b) {
+        buf[b] = static_cast<cplx*>(std::calloc(n, sizeof(cplx)));
+        if (!buf[b]) {
+            for (int c = 0; c < b; ++c) std::free(buf[c]);
+            return -2;
+        }
+    }
+    cplx *k1 = buf[0], *k2 = buf[1], *k3 = buf[2], *k4 = buf[3], *t = buf[4];
+    double best = 0.0;
+    for (int r = 0; r < repeats; ++r) {
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int64_t u = u_begin; u < u_end; u += stride) rhs_ado(m, y, k1, (size_t)u);
+        for (int64_t u = u_begin; u < u_end; u += stride)
+            for (size_t i = u * NN; i < (u + 1) * NN; ++i) t[i] = y[i] + 0.5 * dt_fs * k1[i];
+        for (int64_t u = u_begin; u < u_end; u += stride) rhs_ado(m, t, k2, (size_t)u);
+        for (int64_t u = u_begin; u < u_end; u += stride)
+            for (size_t i = u * NN; i < (u + 1) * NN; ++i) t[i] = y[i] + 0.5 * dt_fs * k2[i];
+        for (int64_t u = u_begin; u < u_end; u += stride) rhs_ado(m, t, k3, (size_t)u);
+        for (int64_t u = u_begin; u < u_end; u += stride)
+            for (size_t i = u * NN; i < (u + 1) * NN; ++i) t[i] = y[i] + dt_fs * k3[i];
+        for (int64_t u = u_begin; u < u_end; u += stride) rhs_ado(m, t, k4, (size_t)u);
+        for (int64_t u = u_begin; u < u_end; u += stride)
+            for (size_t i = u * NN; i < (u + 1) * NN; ++i)
+                t[i] = y[i] + dt_fs / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+        const double sec =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        best = r == 0 ? sec : std::min(best, sec);
+    }
+    *seconds = best;
+    for (int b = 0; b < 5; ++b) std::free(buf[b]);
     return 0;
 }
 
