@@ -633,16 +633,12 @@ def run_absorption(args):
     print(json.dumps(out), flush=True)
 
 
-def run_copy(args):
-    """A plain device-to-device copy of known size: the reference against
-    which the HBM byte counters of a profiler run are scaled."""
-    import torch
-    torch.cuda.set_device(0)
-    n = int(args.copy_gib * (1 << 30)) // 4
+def _device_copy(torch, gib, steps, warmup):
+    """A plain device-to-device copy of `gib` GiB, `steps` times: (elements,
+    seconds).  Bytes moved per copy: 8 per element (read + write)."""
+    n = int(gib * (1 << 30)) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    steps = args.steps if args.steps is not None else 20
-    warmup = args.warmup if args.warmup is not None else 3
     for _ in range(warmup):
         dst.copy_(src)
     torch.cuda.synchronize()
@@ -651,6 +647,19 @@ def run_copy(args):
         dst.copy_(src)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    del src, dst
+    torch.cuda.empty_cache()
+    return n, el
+
+
+def run_copy(args):
+    """A plain device-to-device copy of known size: the reference against
+    which the HBM byte counters of a profiler run are scaled."""
+    import torch
+    torch.cuda.set_device(0)
+    steps = args.steps if args.steps is not None else 20
+    warmup = args.warmup if args.warmup is not None else 3
+    n, el = _device_copy(torch, args.copy_gib, steps, warmup)
     print(json.dumps({"workload": "copy", "bytes_read_per_copy": 4 * n,
                       "bytes_written_per_copy": 4 * n, "steps": steps,
                       "ms_per_copy": 1e3 * el / steps,
@@ -737,6 +746,10 @@ def main():
     avg_launch_s = ms.value / 1e3 / max(launches.value, 1)
     bytes_per_launch = kbytes.value / max(launches.value, 1)
     achieved = bytes_per_launch / avg_launch_s / 1e9
+    # what a plain 4 GiB device copy (read + write) sustains on this GPU, the
+    # practical ceiling of a read/write stream next to the datasheet peak
+    n_copy, t_copy = _device_copy(torch, 4.0, 20, 3)
+    copy_gbs = 8.0 * n_copy * 20 / t_copy / 1e9
     pops = rec[-1, :N]
     print("ms/step %.3f  ADO-updates/s %.3e  alg HBM %.0f GB/s  bulk kernel avg %.3f ms "
           "(%.0f GB/s)  trace %.15f" % (ms_per_step, ado_updates, hbm_gbs, avg_launch_s * 1e3,
@@ -801,6 +814,8 @@ def main():
             "bytes_per_launch_algorithmic": bytes_per_launch,
             "table_bytes_per_launch": _table_bytes_per_launch(
                 kernel_short, n, W_modes, prob["depth"], precision == heom.FP64),
+            "device_copy_GBps": copy_gbs,
+            "frac_of_device_copy": achieved / copy_gbs,
         },
         "cpu_baseline": cpu,
         "fp64": fp64,
