@@ -175,7 +175,7 @@ __host__ __device__ inline FmaLds fma_lds(int N, int W, int D, int GA, int tsize
 // and thread.  W = 0 for the top-level launch (no "+" links).  Offsets in
 // bytes, 16-byte aligned.
 struct SmallLds {
-    size_t h, delta, begin, rows, part, slot0, slot_bytes, total;
+    size_t h, delta, begin, rows, comb, part, slot0, slot_bytes, total;
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -189,6 +189,8 @@ __host__ __device__ inline SmallLds small_lds(int N, int W, int D, int GA, int t
     L.delta = o; o = align16(o + (size_t)N * tsize);
     L.begin = o; o = align16(o + (size_t)(N + 1 + 2 * W) * 4);
     L.rows = o; o = align16(o + 2 * G * (Dm + W) * N * (herm ? 1 : 2) * tsize);
+    // Hermitian: the weighted "-" rows of each ADO summed per state [G][N][N]
+    L.comb = o; o = align16(o + (herm ? 2 * G * NN * tsize : 0));
     L.part = o; o = align16(o + (el > 1 ? 2 * (size_t)el * 256 * tsize : 0));
     L.slot_bytes = align16((size_t)tsize * (2 * G * NN + 2 * G * Dm + G * W + G) +
                            4 * (2 * G * Dm + G * W));
