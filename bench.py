@@ -56,14 +56,19 @@ def _mix_largest():
     return run
 
 
-KERNEL_SOURCES = ("heom_kernels.hip", "heom_stage_persist.inc", "heom_stage_small.inc")
+# the device sources that define each stage kernel (its own file and the
+# shared helpers and launchers)
+KERNEL_SOURCES = {
+    "k_stage_persist": ("heom_kernels.hip", "heom_stage_persist.inc"),
+    "k_stage_small": ("heom_kernels.hip", "heom_stage_small.inc"),
+}
 
 
-def _kernel_source_digest():
-    """SHA-256 over the device sources, in the order of KERNEL_SOURCES."""
+def _kernel_source_digest(kernel):
+    """SHA-256 over the device sources of `kernel`, in the order listed."""
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in KERNEL_SOURCES.get(kernel, ("heom_kernels.hip",)):
         with open(os.path.join(ROOT, "paper_1803_03498_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -82,7 +87,7 @@ def measured_traffic(kernel, workload, precision):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-    if fields.get("kernel_source_sha256") != _kernel_source_digest():
+    if fields.get("kernel_source_sha256") != _kernel_source_digest(kernel):
         return None
     try:
         return float(fields["traffic_bytes_per_launch"])
