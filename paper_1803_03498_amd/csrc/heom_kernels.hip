@@ -2092,7 +2092,8 @@ static hipError_t launch_persist_t(const Job& single, int total_tiles, const Sta
     // sigma_0 rides along when its staging fits the LDS that the register
     // limit leaves to each resident workgroup
     // two workers per CU for N > 32 (measured faster than the three that the
-    // registers of the stage without bases allow)
+    // registers of the stage without bases allow); up to sixteen 2-wave
+    // workers for N <= 16
     const int cap = NB >= 3 ? 2 : 16;
     int by_regs = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&by_regs, fn, NT, own) != hipSuccess || by_regs < 1)
@@ -2135,9 +2136,9 @@ static hipError_t launch_persist_nb(const Job& single, int total_tiles, const St
 // Hermitian ADOs with a real H and 10 <= N <= 64.  Below N = 10 an ADO fills
 // too little of a 16 x 16 matrix-core tile, and tiles of several ADOs on the
 // FMA path are faster (the 12.3M-ADO (6, 6) FMO reference at N = 7: 17.8 ms
-// per stage here, 15.9 ms on the one-launch FMA kernel, 8.4 ms on the
-// persistent FMA kernel; at N = 14, 237k ADOs: 0.39 ms here against 1.18 ms
-// on the one-launch FMA kernel).
+// per stage here, 15.9 ms on the one-launch FMA kernel, 6.6 ms on the
+// persistent FMA kernel; at N = 14, 237k ADOs: 0.34 ms here against 0.49 ms
+// on the persistent FMA kernel and 1.18 ms on the one-launch FMA kernel).
 static int persist_blocks(const Job& single, bool batched) {
     if (batched || single.herm == 0 || single.t.h_complex != 0 || single.t.N < 10 ||
         single.t.N > 64)
