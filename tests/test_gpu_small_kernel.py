@@ -59,3 +59,26 @@ def test_small_kernel_matches_oracle(heom, orc, name, seed, N, M, D, herm, cplx,
     print("  max error / max element %.3e" % (err / scale), flush=True)
     assert err <= tol * scale
     assert np.max(np.abs(rec[:, :N] - rec_ref[:, :N])) <= tol * max(1.0, np.max(np.abs(rec_ref[:, :N])))
+
+
+def test_small_kernel_n16_fp64_matches_oracle(heom, orc):
+    # N = 16: N^2 = 256, the largest divisor of the kernel's index decode;
+    # eight baths at depth 10 (43758 ADOs), FP64 (FP32 at N >= 10 takes the
+    # matrix-core kernel); one RK4 step (all four stage forms) against the
+    # oracle element by element
+    _case("small kernel N16 fp64")
+    prob = hi.random_problem(74, 16, n_baths=8, M=0, D=10)
+    W, n = orc.sizes(prob)
+    assert W == 8 and n == 43758
+    x0 = hi.random_state(174, n, 16, hermitian=True, scale=0.1)
+    x0[0] = hi.population_rho0(16, 8)
+    y_ref, rec_ref = orc.propagate(prob, x0, 0.5, 1, 1)
+    h = heom.Hierarchy(prob, 0)
+    st = h.state_from_numpy(x0)
+    rec = h.propagate(st, 0.5, 1, 1, hermitian=True)
+    y = h.state_to_numpy(st)
+    scale = np.max(np.abs(y_ref))
+    err = np.max(np.abs(y - y_ref))
+    print("  max error / max element %.3e" % (err / scale), flush=True)
+    assert err <= 1e-12 * scale
+    assert np.max(np.abs(rec[:, :16] - rec_ref[:, :16])) <= 1e-12 * max(1.0, np.max(np.abs(rec_ref[:, :16])))
