@@ -690,7 +690,7 @@ def main():
         run_serve(args)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     # the serving mix's oracle leg spawns its host processes before any GPU work
