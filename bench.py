@@ -124,41 +124,39 @@ def parse():
 
 
 def cpu_baseline(prob, target_s):
-    """Time the FP64 oracle on a bounded sample of the same workload: the
-    right-hand side of a contiguous block of the deepest ADOs (the level that
-    holds most of the hierarchy), single-threaded on this host.  One
-    ADO-update is four right-hand-side evaluations."""
+    """Time the FP64 oracle on a bounded sample of the same workload,
+    single-threaded on this host: the oracle's own RK4 step code (four
+    evaluations and the vector updates) over every k-th ADO of the
+    hierarchy, all levels, with the model built outside the timed region
+    (oracle.time_step_sample); k is set from a first probe so that the
+    sample takes about target_s.  One ADO-update is one ADO advanced by one
+    RK4 step."""
     import oracle
-    W, n = oracle.sizes(prob)
+    _, n = oracle.sizes(prob)
     N = prob["H"].shape[0]
     x = np.zeros((n, N, N), np.complex128)  # pages are touched only where read
     x[0] = prob["rho0"]
     t0 = time.perf_counter()
     oracle.rhs(prob, x, 0, 0)  # model and table construction only
     t_setup = time.perf_counter() - t0
-    # probe with growing blocks, then one timed block sized to target_s
-    k = 1
-    while True:
-        t0 = time.perf_counter()
-        oracle.rhs(prob, x, n - k, n)
-        dt = time.perf_counter() - t0 - t_setup
-        if dt > 0.1 * target_s or k >= n:
-            break
-        k = min(n, max(k * 2, int(k * 0.2 * target_s / max(dt, 1e-3))))
-    if k < n:
-        k = min(n, max(k, int(k * target_s / max(dt, 1e-6))))
-        t0 = time.perf_counter()
-        oracle.rhs(prob, x, n - k, n)
-        dt = time.perf_counter() - t0 - t_setup
-    per_rhs = max(dt, 1e-9) / k
-    return {"value": 1.0 / (4.0 * per_rhs), "unit": "ADO-updates/s", "cores": 1,
+    stride = max(1, n // 256)
+    sec = oracle.time_step_sample(prob, x, prob["dt_fs"], 0, n, stride, 1)
+    per_ado = max(sec, 1e-9) / ((n + stride - 1) // stride)
+    stride = max(1, min(stride, int(n * per_ado / target_s)))
+    # a step shorter than the target is repeated (the fastest repetition)
+    reps = 1 if stride > 1 else max(1, min(100, int(target_s / max(per_ado * n, 1e-9))))
+    sec = oracle.time_step_sample(prob, x, prob["dt_fs"], 0, n, stride, reps)
+    k = (n + stride - 1) // stride
+    which = ("every ADO" if stride == 1 else "every %d-th ADO" % stride)
+    return {"value": k / max(sec, 1e-9), "unit": "ADO-updates/s", "cores": 1,
             "kind": "oracle",
             "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
             "threads_available": len(os.sched_getaffinity(0)),
-            "sample": "FP64 oracle right-hand side of the last %d ADOs (depth-%d level) of %s, "
-                      "%.1f s of CPU on one thread; one ADO-update = 4 evaluations; model "
-                      "setup (%.1f s) excluded" % (k, prob["depth"], prob.get("name", "?"), dt,
-                                                   t_setup)}
+            "sample": "FP64 oracle RK4 step (four right-hand sides and the vector updates) "
+                      "over %s of %s (%d of %d, all levels), %.2f s of CPU on one thread%s; "
+                      "model setup (%.1f s per build) outside the timed region"
+                      % (which, prob.get("name", "?"), k, n, sec,
+                         ", fastest of %d repetitions" % reps if reps > 1 else "", t_setup)}
 
 
 def _cpu_model():
