@@ -96,3 +96,23 @@ def test_oracle_request_seconds_small_request():
     sec, stride = bench._oracle_request_seconds((r["runs"], 1000, 0.5))
     assert stride == 1  # a small request is timed over all of its ADOs
     assert sec > 0.0
+
+
+def test_serve_cpu_baseline_summary():
+    # requests/s of P cores each running whole requests one after another:
+    # P / mean request time, over the first n requests only
+    cpu = {"seconds": [10.0, 30.0, 20.0, 1000.0], "steps_timed": [1, 1, 5, 1],
+           "procs": 4, "budget_s": 1.5, "wall_s": 3.0}
+    out = bench._serve_cpu_baseline(cpu, 3)
+    assert out["value"] == pytest.approx(4 / 20.0)
+    assert out["cores"] == 4 and out["unit"] == "req/s" and out["kind"] == "oracle"
+    assert out["p50_request_s_one_core"] == pytest.approx(20.0)
+    assert "first 3 requests" in out["sample"]
+    # asking for more requests than were timed uses those that were
+    assert bench._serve_cpu_baseline(cpu, 10)["value"] == pytest.approx(4 / 265.0)
+
+
+def test_cpu_baseline_dimer():
+    out = bench.cpu_baseline(hi.dimer(), 0.2)
+    assert out["value"] > 0.0 and out["cores"] == 1 and out["kind"] == "oracle"
+    assert "every ADO of dimer" in out["sample"]
